@@ -1,0 +1,275 @@
+"""Pins of the oracle's geometry, residual, tangent, energy and adjoint (CPU only).
+
+Each check is fixed by mathematics rather than by the oracle itself: exact volume,
+equilibrium identities of the patch test, rigid motions, objectivity, finite
+differences of the energy and of the residual, the linear-elastic limit assembled from
+the textbook strain-displacement form, and a 50-digit evaluation of ``J - 1``."""
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_2204_01722_amd import inputs
+
+MU, LAM = inputs.lame(1.0, 0.3)
+
+
+def _disc(n=2, p=2, jitter=0.05, L=(1.0, 1.0, 1.0), seed=2204):
+    m = inputs.box_mesh(n, p, L=L, jitter=jitter, seed=seed)
+    return m, fem.make_disc(m.coords, m.elem_nodes, m.P)
+
+
+def _rot(a, b, c):
+    def R(axis, t):
+        cs, sn = np.cos(t), np.sin(t)
+        M = np.eye(3)
+        i, j = [k for k in range(3) if k != axis]
+        M[i, i], M[i, j], M[j, i], M[j, j] = cs, -sn, sn, cs
+        return M
+    return R(0, a) @ R(1, b) @ R(2, c)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_volume_exact(p):
+    m, d = _disc(3, p, jitter=0.08, L=(1.0, 2.0, 0.5))
+    W, _ = fem.qdata(d)
+    assert abs(W.sum() - 1.0) < 1e-13
+
+
+def test_affine_element_determinant():
+    m, d = _disc(2, 2, jitter=0.0, L=(2.0, 2.0, 2.0))
+    W, dxidX = fem.qdata(d)
+    # h = 1 per element, reference cell [-1,1]: det = (1/2)^3
+    np.testing.assert_allclose(W, np.broadcast_to(d.T["w3"][None, :] * 0.125, W.shape), rtol=1e-14)
+    np.testing.assert_allclose(dxidX, np.broadcast_to(2.0 * np.eye(3), dxidX.shape), atol=1e-13)
+
+
+def test_inverted_element_raises():
+    m, d = _disc(2, 2, jitter=0.0)
+    c = m.coords.copy()
+    c[m.elem_nodes[0, 13]] += np.array([2.0, 0.0, 0.0])  # drag the centre node far out
+    d2 = fem.make_disc(c, m.elem_nodes, 3)
+    with pytest.raises(ValueError):
+        fem.qdata(d2)
+
+
+def test_j_minus_1_against_50_digits():
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(11)
+    worst_j, worst_l = 0.0, 0.0
+    for scale in (1e-10, 1e-7, 1e-4, 1e-2, 0.3):
+        H = rng.normal(0, scale, (200, 3, 3))
+        H = H[np.linalg.det(np.eye(3) + H) > 0.1]
+        jm1 = fem.j_minus_1(H)
+        lj = np.log1p(jm1)
+        for k in range(H.shape[0]):
+            M = mpmath.matrix([[mpmath.mpf(float(H[k, i, j])) + (1 if i == j else 0)
+                                for j in range(3)] for i in range(3)])
+            ex = mpmath.det(M) - 1
+            worst_j = max(worst_j, float(abs((jm1[k] - ex) / ex)))
+            worst_l = max(worst_l, float(abs((lj[k] - mpmath.log(ex + 1)) / mpmath.log(ex + 1))))
+    assert worst_j < 1e-13 and worst_l < 1e-13
+
+
+def test_zero_displacement_zero_residual():
+    m, d = _disc(2, 2)
+    assert np.all(fem.residual(d, np.zeros((m.n_nodes, 3)), MU, LAM) == 0.0)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_patch_test_affine(p):
+    """Affine displacement: uniform stress, so every node away from the boundary is in
+    equilibrium and sum_a r_a (x) X_a equals P * volume (exact for linear geometry)."""
+    m, d = _disc(3, p, jitter=0.1)
+    G = np.array([[0.05, 0.02, -0.01], [0.0, -0.03, 0.04], [0.01, 0.0, 0.02]])
+    u = m.coords @ G.T
+    r = fem.residual(d, u, MU, LAM)
+    NX, NY, NZ = m.grid
+    idx = np.arange(m.n_nodes)
+    I, J, K = idx % NX, (idx // NX) % NY, idx // (NX * NY)
+    interior = (I > 0) & (I < NX - 1) & (J > 0) & (J < NY - 1) & (K > 0) & (K < NZ - 1)
+    scale = np.abs(r).max()
+    assert np.abs(r[interior]).max() < 1e-12 * scale
+    P = fem.piola(G[None], np.array([MU]), np.array([LAM]))[0]
+    virial = r.T @ m.coords
+    np.testing.assert_allclose(virial, P * 1.0, atol=1e-13)
+    np.testing.assert_allclose(r.sum(axis=0), 0.0, atol=1e-13)
+
+
+def test_rigid_rotation_zero_residual():
+    m, d = _disc(2, 2, jitter=0.05)
+    R = _rot(0.4, -0.7, 1.1)
+    u = m.coords @ R.T - m.coords
+    r = fem.residual(d, u, MU, LAM)
+    assert np.abs(r).max() < 1e-14
+
+
+def test_objectivity():
+    m, d = _disc(2, 2, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    R = _rot(0.3, 0.2, -0.5)
+    u2 = (m.coords + u) @ R.T - m.coords
+    r1 = fem.residual(d, u, MU, LAM)
+    r2 = fem.residual(d, u2, MU, LAM)
+    np.testing.assert_allclose(r2, r1 @ R.T, atol=1e-14 * np.abs(r1).max() * 10)
+
+
+def test_residual_is_energy_gradient():
+    m, d = _disc(2, 2, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    w = inputs.random_vector(m.n_nodes, 5)
+    h = 1e-5
+    fd = (fem.energy(d, u + h * w, MU, LAM) - fem.energy(d, u - h * w, MU, LAM)) / (2 * h)
+    an = np.sum(fem.residual(d, u, MU, LAM) * w)
+    assert abs(fd - an) <= 1e-7 * abs(an)
+
+
+def test_jacobian_central_differences():
+    m, d = _disc(2, 2, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    w = inputs.random_vector(m.n_nodes, 6)
+    h = 1e-6
+    fd = (fem.residual(d, u + h * w, MU, LAM) - fem.residual(d, u - h * w, MU, LAM)) / (2 * h)
+    y = fem.jacobian_apply(d, u, w, MU, LAM)
+    assert np.linalg.norm(fd - y) <= 1e-8 * np.linalg.norm(y)
+
+
+def test_jacobian_symmetric_and_matches_assembly():
+    m, d = _disc(2, 2, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    K = fem.tangent_matrix(d, u, MU, LAM)
+    v = inputs.random_vector(m.n_nodes, 7).reshape(-1)
+    w = inputs.random_vector(m.n_nodes, 8).reshape(-1)
+    assert abs(v @ (K @ w) - w @ (K @ v)) <= 1e-13 * abs(v @ (K @ w))
+    y = fem.jacobian_apply(d, u, w, MU, LAM).reshape(-1)
+    np.testing.assert_allclose(y, K @ w, atol=1e-13 * np.abs(y).max())
+
+
+def test_jacobian_with_mask_identity_rows():
+    m, d = _disc(2, 2, jitter=0.05)
+    mask = inputs.face_mask(m, {"x0": (1, 1, 1), "x1": (1, 0, 0)})
+    u = inputs.config1_u(m, amplitude=0.05)
+    w = inputs.random_vector(m.n_nodes, 9)
+    y = fem.jacobian_apply(d, u, w, MU, LAM, mask=mask)
+    mb = mask.astype(bool)
+    np.testing.assert_array_equal(y[mb], w[mb])
+    Kb = fem.apply_bc(fem.tangent_matrix(d, u, MU, LAM), mask)
+    np.testing.assert_allclose(y.reshape(-1), Kb @ w.reshape(-1), atol=1e-13 * np.abs(y).max())
+    diag = fem.diagonal(d, u, MU, LAM, mask)
+    assert np.all(diag[mb] == 1.0)
+
+
+def _linear_elastic_stiffness(m, d, mu, lam):
+    """Independent textbook assembly: K_e = sum_q W B^T D B with the Voigt
+    strain-displacement matrix B (6 x 3P^3) and isotropic elasticity matrix D."""
+    D = np.zeros((6, 6))
+    D[:3, :3] = lam
+    D[:3, :3] += 2 * mu * np.eye(3)
+    D[3:, 3:] = mu * np.eye(3)
+    W, _, gp = fem.geometry(d)
+    E, Q3, _, P3 = gp.shape
+    Ke = np.zeros((E, 3 * P3, 3 * P3))
+    for e in range(E):
+        for q in range(Q3):
+            B = np.zeros((6, 3 * P3))
+            for a in range(P3):
+                gx, gy, gz = gp[e, q, :, a]
+                B[0, 3 * a + 0] = gx
+                B[1, 3 * a + 1] = gy
+                B[2, 3 * a + 2] = gz
+                B[3, 3 * a + 1], B[3, 3 * a + 2] = gz, gy   # gamma_yz
+                B[4, 3 * a + 0], B[4, 3 * a + 2] = gz, gx   # gamma_xz
+                B[5, 3 * a + 0], B[5, 3 * a + 1] = gy, gx   # gamma_xy
+            Ke[e] += W[e, q] * B.T @ D @ B
+    return fem.assemble(m.elem_nodes, Ke, m.n_nodes)
+
+
+def test_linear_elastic_limit():
+    m, d = _disc(2, 2, jitter=0.05)
+    K0 = fem.tangent_matrix(d, np.zeros((m.n_nodes, 3)), MU, LAM)
+    Kl = _linear_elastic_stiffness(m, d, MU, LAM)
+    diff = abs(K0 - Kl).max()
+    assert diff <= 1e-13 * abs(Kl).max()
+    t = np.tile([1.0, -2.0, 0.5], m.n_nodes)
+    assert np.abs(K0 @ t).max() <= 1e-13 * abs(Kl).max()
+
+
+def test_energy_rotation_and_material_derivative():
+    m, d = _disc(2, 2, jitter=0.05)
+    R = _rot(0.2, 0.9, -0.3)
+    assert abs(fem.energy(d, m.coords @ R.T - m.coords, MU, LAM)) < 1e-14
+    # dPsi/dmu_e = sum W (tr e - log J); dPsi/dlambda_e = sum W (log J)^2 / 2
+    u = inputs.config1_u(m, amplitude=0.05)
+    E = m.n_elem
+    mu = np.full(E, MU)
+    lam = np.full(E, LAM)
+    W, _, gp = fem.geometry(d)
+    H = np.einsum("eai,eqJa->eqiJ", u[m.elem_nodes], gp)
+    logJ = np.log1p(fem.j_minus_1(H))
+    tre = np.trace(H, axis1=-2, axis2=-1) + 0.5 * np.sum(H * H, axis=(-1, -2))
+    for e in (0, 5):
+        h = 1e-6
+        mp, mm = mu.copy(), mu.copy()
+        mp[e] += h
+        mm[e] -= h
+        fd = (fem.energy(d, u, mp, lam) - fem.energy(d, u, mm, lam)) / (2 * h)
+        assert abs(fd - np.sum(W[e] * (tre[e] - logJ[e]))) < 1e-9
+        lp, lm = lam.copy(), lam.copy()
+        lp[e] += h
+        lm[e] -= h
+        fd = (fem.energy(d, u, mu, lp) - fem.energy(d, u, mu, lm)) / (2 * h)
+        assert abs(fd - np.sum(W[e] * 0.5 * logJ[e] ** 2)) < 1e-9
+
+
+def test_vjp_dot_product_and_parameter_gradients():
+    m, d = _disc(2, 2, jitter=0.05)
+    mask = inputs.face_mask(m, {"x0": (1, 1, 1)})
+    u = inputs.config1_u(m, amplitude=0.05)
+    mu, lam = inputs.loguniform_materials(m.n_elem, seed=4)
+    w = inputs.random_vector(m.n_nodes, 5)
+    v = inputs.random_vector(m.n_nodes, 12)
+    ub, mub, lamb = fem.residual_vjp(d, u, w, mu, lam, mask)
+    # <w, dr/du v> by central differences of the masked residual
+    h = 1e-6
+    jv = (fem.residual(d, u + h * v, mu, lam, mask) - fem.residual(d, u - h * v, mu, lam, mask)) / (2 * h)
+    assert abs(np.sum(w * jv) - np.sum(ub * v)) <= 1e-8 * abs(np.sum(ub * v))
+    # exact dot-product identity against the assembled tangent
+    K = fem.tangent_matrix(d, u, mu, lam)
+    fr = 1.0 - mask.reshape(-1)
+    lhs = (w.reshape(-1) * fr) @ (K @ v.reshape(-1))
+    assert abs(lhs - np.sum(ub * v)) <= 1e-13 * abs(lhs)
+    # parameter gradients by central differences (h = 1e-6)
+    for e in (0, 3, 7):
+        mp, mm = mu.copy(), mu.copy()
+        mp[e] += h
+        mm[e] -= h
+        fd = np.sum(w * (fem.residual(d, u, mp, lam, mask) - fem.residual(d, u, mm, lam, mask))) / (2 * h)
+        assert abs(fd - mub[e]) <= 1e-7 * max(abs(mub[e]), 1e-3)
+        lp, lm = lam.copy(), lam.copy()
+        lp[e] += h
+        lm[e] -= h
+        fd = np.sum(w * (fem.residual(d, u, mu, lp, mask) - fem.residual(d, u, mu, lm, mask))) / (2 * h)
+        assert abs(fd - lamb[e]) <= 1e-7 * max(abs(lamb[e]), 1e-3)
+
+
+def test_vjp_mu_bar_is_mixed_energy_derivative():
+    """mu_bar_e(u, w) = d/dt dPsi/dmu_e(u + t w) at t = 0 (no mask)."""
+    m, d = _disc(2, 2, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    w = inputs.random_vector(m.n_nodes, 5)
+    mu = np.full(m.n_elem, MU)
+    lam = np.full(m.n_elem, LAM)
+    _, mub, lamb = fem.residual_vjp(d, u, w, mu, lam)
+    W, _, gp = fem.geometry(d)
+
+    def dpsi(v):
+        H = np.einsum("eai,eqJa->eqiJ", v[m.elem_nodes], gp)
+        logJ = np.log1p(fem.j_minus_1(H))
+        tre = np.trace(H, axis1=-2, axis2=-1) + 0.5 * np.sum(H * H, axis=(-1, -2))
+        return np.sum(W * (tre - logJ), axis=1), np.sum(W * 0.5 * logJ ** 2, axis=1)
+
+    h = 1e-5
+    a1, b1 = dpsi(u + h * w)
+    a0, b0 = dpsi(u - h * w)
+    np.testing.assert_allclose((a1 - a0) / (2 * h), mub, rtol=1e-7, atol=1e-10)
+    np.testing.assert_allclose((b1 - b0) / (2 * h), lamb, rtol=1e-6, atol=1e-10)

@@ -1,0 +1,194 @@
+"""Pins of the oracle's multigrid pieces and solver drivers (CPU only): interpolation of
+affine fields, the exact-Galerkin identity of coarse operators built on the fine
+quadrature, the closed-form Chebyshev error polynomial, Ritz bounds of the eigenvalue
+estimate, flexible CG against a direct solve, symmetry of the V-cycle, and the
+homogeneous uniaxial-stretch solution of the Newton driver."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import basis, fem, mg
+from paper_2204_01722_amd import inputs
+
+MU, LAM = inputs.lame(1.0, 0.3)
+
+
+def _levels(n=2, pf=2, pc=1, jitter=0.05):
+    mf = inputs.box_mesh(n, pf, jitter=jitter)
+    mc = inputs.box_mesh(n, pc, jitter=jitter)
+    Pm = mg.prolongation(mf.elem_nodes, mf.P, mf.n_nodes, mc.elem_nodes, mc.P, mc.n_nodes)
+    return mf, mc, Pm
+
+
+@pytest.mark.parametrize("pf,pc", [(2, 1), (4, 2), (3, 1), (4, 1)])
+def test_prolongation_exact_for_affine(pf, pc):
+    mf, mc, Pm = _levels(2, pf, pc, jitter=0.08)
+    G = np.array([[0.3, -0.1, 0.2], [0.05, 0.4, -0.2], [0.1, 0.0, -0.3]])
+    b = np.array([0.1, -0.2, 0.3])
+    fc = mc.coords @ G.T + b
+    ff = mf.coords @ G.T + b
+    np.testing.assert_allclose((Pm @ fc.reshape(-1)).reshape(-1, 3), ff, atol=1e-14)
+
+
+def test_prolongation_preserves_face_zero():
+    mf, mc, Pm = _levels(2, 2, 1)
+    maskc = inputs.face_mask(mc, {"x0": (1, 1, 1)}).astype(bool)
+    maskf = inputs.face_mask(mf, {"x0": (1, 1, 1)}).astype(bool)
+    v = inputs.random_vector(mc.n_nodes, 3)
+    v[maskc] = 0.0
+    assert np.all((Pm @ v.reshape(-1)).reshape(-1, 3)[maskf] == 0.0)
+
+
+@pytest.mark.parametrize("pf,pc", [(2, 1), (3, 1), (4, 2)])
+def test_galerkin_identity(pf, pc):
+    """A coarse operator rediscretised with the coarse basis on the fine quadrature and
+    the fine linearisation equals P^T K_f P (Section III-B: exact Galerkin)."""
+    mf, mc, Pm = _levels(2, pf, pc, jitter=0.06)
+    df = fem.make_disc(mf.coords, mf.elem_nodes, mf.P)
+    u = inputs.config1_u(mf, amplitude=0.05)
+    Kf = fem.tangent_matrix(df, u, MU, LAM)
+    _, dxidX, _ = fem.geometry(df)
+    Tc = basis.tensor_3d(mc.P, mf.P)
+    gpc = np.einsum("dqa,eqdJ->eqJa", Tc["dPhi"], dxidX)
+    Ke_c = fem.element_matrices(df, u, MU, LAM, grad_override=gpc)
+    Kc = fem.assemble(mc.elem_nodes, Ke_c, mc.n_nodes)
+    G = mg.galerkin(Kf, Pm)
+    assert abs(G - Kc).max() <= 1e-13 * abs(Kc).max()
+
+
+def test_chebyshev_closed_form():
+    mf = inputs.box_mesh(2, 2, jitter=0.05)
+    d = fem.make_disc(mf.coords, mf.elem_nodes, 3)
+    mask = inputs.face_mask(mf, {"x0": (1, 1, 1)})
+    A = fem.apply_bc(fem.tangent_matrix(d, inputs.config1_u(mf), MU, LAM), mask).toarray()
+    Dg = np.diag(A)
+    dinv = 1.0 / Dg
+    lam_max = 1.7
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=A.shape[0])
+    x0 = rng.normal(size=A.shape[0])
+    xs = np.linalg.solve(A, b)
+    for m in (1, 2, 3, 5):
+        x = mg.chebyshev(A, dinv, b, x0, lam_max, m)
+        a, bb = 0.1 * lam_max, 1.1 * lam_max
+        th, de = 0.5 * (a + bb), 0.5 * (bb - a)
+        S = np.diag(np.sqrt(dinv)) @ A @ np.diag(np.sqrt(dinv))
+        ev, V = np.linalg.eigh(S)
+        Tm = np.polynomial.chebyshev.Chebyshev.basis(m)
+        pol = Tm((th - ev) / de) / Tm(th / de)
+        e0 = np.sqrt(Dg) * (xs - x0)
+        em = (V @ (pol * (V.T @ e0))) / np.sqrt(Dg)
+        np.testing.assert_allclose(xs - x, em, atol=1e-11 * np.abs(xs).max())
+
+
+def test_lambda_max_estimate_bounds():
+    mf = inputs.box_mesh(3, 2, jitter=0.05)
+    d = fem.make_disc(mf.coords, mf.elem_nodes, 3)
+    mask = inputs.face_mask(mf, {"x0": (1, 1, 1)})
+    A = fem.apply_bc(fem.tangent_matrix(d, inputs.config1_u(mf), MU, LAM), mask)
+    dinv = 1.0 / A.diagonal()
+    seed = inputs.rough_seed(mf.n_nodes, mask, 7).reshape(-1)
+    est = mg.estimate_lambda_max(A, dinv, seed, 10)
+    Ad = A.toarray()
+    S = np.diag(np.sqrt(dinv)) @ Ad @ np.diag(np.sqrt(dinv))
+    true = np.linalg.eigvalsh(S).max()
+    assert est <= true * (1 + 1e-12)
+    assert est >= 0.8 * true
+
+
+def _two_level(n=2, pf=2, pc=1, coarse_fixed=None, coarse_rtol=1e-3, degree=3):
+    mf, mc, Pm = _levels(n, pf, pc)
+    d = fem.make_disc(mf.coords, mf.elem_nodes, mf.P)
+    maskf = inputs.face_mask(mf, {"x0": (1, 1, 1)})
+    maskc = inputs.face_mask(mc, {"x0": (1, 1, 1)})
+    u = inputs.config1_u(mf, amplitude=0.05)
+    K = fem.tangent_matrix(d, u, MU, LAM)
+    seeds = [inputs.rough_seed(mf.n_nodes, maskf, 7)]
+    V = mg.VCycle(K, [Pm], [maskf, maskc], seeds, degree=degree, coarse_rtol=coarse_rtol,
+                  coarse_fixed=coarse_fixed)
+    return mf, maskf, V
+
+
+def test_vcycle_symmetric_with_exact_coarse_solve():
+    mf, maskf, V = _two_level(coarse_rtol=1e-15, coarse_fixed=None)
+    rng = np.random.default_rng(1)
+    fr = 1.0 - maskf.reshape(-1)
+    v = rng.normal(size=3 * mf.n_nodes) * fr
+    w = rng.normal(size=3 * mf.n_nodes) * fr
+    a, b = v @ V(w), w @ V(v)
+    assert abs(a - b) <= 1e-10 * abs(a)
+
+
+def test_fcg_matches_direct_solve():
+    mf, maskf, V = _two_level()
+    A = V.ops[0]
+    rng = np.random.default_rng(2)
+    b = rng.normal(size=A.shape[0]) * (1.0 - maskf.reshape(-1))
+    x, its, rel = mg.fcg(A, V, b, rtol=1e-10, maxit=200)
+    xs = spla.spsolve(A.tocsc(), b)
+    assert rel <= 1e-10
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert its < 100
+
+
+def _uniaxial_stretch(lx, mu, lam):
+    """Lateral stretch t with mu (t^2 - 1) + lambda log(lx t^2) = 0 (scalar Newton)."""
+    t = 1.0
+    for _ in range(50):
+        f = mu * (t * t - 1) + lam * np.log(lx * t * t)
+        df = 2 * mu * t + 2 * lam / t
+        t -= f / df
+    return t
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_newton_uniaxial_closed_form(p):
+    m = inputs.box_mesh(2, p, jitter=0.1)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    mask = inputs.face_mask(m, {"x0": (1, 0, 0), "y0": (0, 1, 0), "z0": (0, 0, 1), "x1": (1, 0, 0)})
+    delta = 0.3
+    lift = inputs.affine_lifting(m, (delta, 0.0, 0.0))
+
+    def solve(K, rhs):
+        return spla.spsolve(K.tocsc(), rhs)
+
+    u, hist = mg.newton_load_steps(d, MU, LAM, mask, lift, 3, solve, rtol=1e-10)
+    lx = 1.0 + delta
+    lt = _uniaxial_stretch(lx, MU, LAM)
+    exact = m.coords * np.array([lx - 1.0, lt - 1.0, lt - 1.0])
+    np.testing.assert_allclose(u, exact, atol=1e-10)
+    assert max(hist) <= 8
+
+
+def test_newton_with_pmg_fcg():
+    """Newton-FCG with the p-MG V-cycle (Q2 -> Q1) reaches the direct-solve answer."""
+    mf, mc, Pm = _levels(2, 2, 1)
+    d = fem.make_disc(mf.coords, mf.elem_nodes, 3)
+    maskf = inputs.face_mask(mf, {"x0": (1, 1, 1), "x1": (1, 1, 1)})
+    maskc = inputs.face_mask(mc, {"x0": (1, 1, 1), "x1": (1, 1, 1)})
+    lift = inputs.affine_lifting(mf, (0.1, 0.0, 0.0))
+    ctx = {}
+
+    def solve_pmg(K, rhs):
+        Kraw = fem.tangent_matrix(d, ctx["u"], MU, LAM)
+        V = mg.VCycle(Kraw, [Pm], [maskf, maskc], [inputs.rough_seed(mf.n_nodes, maskf)])
+        x, _, _ = mg.fcg(K, V, rhs, rtol=1e-10)
+        return x
+
+    def solve_direct(K, rhs):
+        return spla.spsolve(K.tocsc(), rhs)
+
+    # the driver calls linear_solve with the tangent at the current u; record u
+    orig = fem.tangent_matrix
+
+    def tracking(disc, u, mu, lam):
+        ctx["u"] = u
+        return orig(disc, u, mu, lam)
+
+    fem.tangent_matrix = tracking
+    try:
+        u1, h1 = mg.newton_load_steps(d, MU, LAM, maskf, lift, 2, solve_pmg, rtol=1e-9)
+    finally:
+        fem.tangent_matrix = orig
+    u2, h2 = mg.newton_load_steps(d, MU, LAM, maskf, lift, 2, solve_direct, rtol=1e-9)
+    np.testing.assert_allclose(u1, u2, atol=1e-9)
