@@ -1,0 +1,243 @@
+/*
+ * hpmg.h - C ABI of the MI355X (gfx950) matrix-free Neo-Hookean operator and its
+ * p-multigrid solver (arXiv:2204.01722, "Performance-Portable Solid Mechanics via
+ * Matrix-Free p-Multigrid").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function is extern "C", returns an hpmg_status (0 = HPMG_OK), never throws
+ *   and never exits.  On failure hpmg_last_error() (thread-local) holds a message.
+ * - Device buffers are owned by the caller (the Python layer allocates them with
+ *   PyTorch); the library performs no device allocation.  Handles own host metadata
+ *   only and borrow every device pointer passed to them, which must outlive the handle.
+ * - All device work is enqueued on the hipStream_t passed as `stream` (NULL = default
+ *   stream) and is asynchronous unless a function says it synchronises.
+ * - L-vectors are [n_nodes][3] with the three displacement components interleaved.
+ *   Element-to-node maps are int32 [n_elem][P^3], element-local nodes lexicographic
+ *   with xi_1 fastest.  Pointers must be 8-byte aligned (PyTorch allocations are).
+ * - Argument and shape errors are detected on the host before any launch.  Errors
+ *   found on the device (non-positive Jacobian determinant, non-finite values) set
+ *   bits in a per-operator flag word read by hpmg_op_query_flags.
+ * - Dirichlet mask (uint8 [n_nodes][3], 1 = constrained component): the residual's
+ *   constrained rows are zero; the Jacobian apply is M J M + (I - M) with
+ *   M = diag(1 - mask) (constrained rows are the identity); the diagonal is 1 there.
+ * - Outputs are overwritten, not accumulated, unless the name says "add".
+ * - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ */
+#ifndef HPMG_H
+#define HPMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPMG_OK = 0,
+  HPMG_ERR_ARG = 1,           /* null pointer, bad enum, bad scalar */
+  HPMG_ERR_SHAPE = 2,         /* sizes inconsistent with the handle */
+  HPMG_ERR_UNSUPPORTED = 3,   /* (P, Q) pair or mode not compiled */
+  HPMG_ERR_WORKSPACE = 4,     /* workspace missing or too small */
+  HPMG_ERR_HIP = 5,           /* a HIP runtime call failed */
+  HPMG_ERR_NONPOSITIVE_J = 6, /* a determinant <= 0 was found on the device */
+  HPMG_ERR_NONFINITE = 7,     /* NaN/Inf found on the device */
+  HPMG_ERR_BREAKDOWN = 8,     /* Krylov breakdown (p^T A p <= 0 or 0/0) */
+  HPMG_ERR_NOT_CONVERGED = 9  /* iteration limit reached */
+} hpmg_status;
+
+typedef enum { HPMG_F64 = 0, HPMG_F32 = 1 } hpmg_precision;
+typedef enum { HPMG_STORED = 0, HPMG_RECOMPUTE = 1 } hpmg_mode;
+
+/* Device flag bits reported by hpmg_op_query_flags. */
+#define HPMG_FLAG_NONPOSITIVE_J 1u
+#define HPMG_FLAG_NONFINITE 2u
+#define HPMG_FLAG_BAD_INDEX 4u
+
+typedef struct hpmg_op_s *hpmg_op;
+typedef struct hpmg_mg_s *hpmg_mg;
+
+/* ---------------------------------------------------------------------------------
+ * Diagnostics
+ * --------------------------------------------------------------------------------- */
+const char *hpmg_status_string(int status);
+/* Message of the last failing call on this thread ("" if none). */
+const char *hpmg_last_error(void);
+/* Library version string and the HIP device architecture it was compiled for. */
+const char *hpmg_version(void);
+
+/* ---------------------------------------------------------------------------------
+ * Reference-element tables (Section II-B, eq. tensorDense; host only, no GPU needed).
+ * P = p + 1 Gauss-Lobatto nodes, Q Gauss-Legendre points on [-1, 1].
+ *   interp [Q][P]  B_I[q][i]  = l_i(x_q)
+ *   grad   [Q][P]  B_xi[q][i] = l_i'(x_q)
+ *   colloc [Q][Q]  collocated derivative B_xi B_I^+ (requires Q >= P, Section II-B)
+ *   qref [Q], qweight [Q], gll [P]
+ * Any output pointer may be NULL.  Returns HPMG_ERR_ARG for P < 2, Q < P or Q > 16.
+ * --------------------------------------------------------------------------------- */
+int hpmg_basis_tabulate(int P, int Q, double *interp, double *grad, double *colloc,
+                        double *qref, double *qweight, double *gll);
+/* Coarse-to-fine interpolation table [Pf][Pc]: coarse Lagrange basis (Pc GLL nodes)
+ * evaluated at the Pf GLL nodes (the 1D factor of B_ctof in eq. mg_prolong). */
+int hpmg_basis_ctof(int Pf, int Pc, double *ctof);
+
+/* ---------------------------------------------------------------------------------
+ * Operator handles (one per multigrid level; eq. libceed_representation restricted
+ * to one device: E^T B^T D B E).
+ * --------------------------------------------------------------------------------- */
+/* Fine operator: order P-1 elements with Q^3 Gauss points.  elem_nodes: device int32
+ * [n_elem][P^3] with ids in [0, n_nodes); mask: device uint8 [n_nodes][3] or NULL.
+ * Supported (P, Q): 2 <= P <= 5, P <= Q <= 5 (and (5, 6)). */
+int hpmg_op_create(int P, int Q, int64_t n_elem, int64_t n_nodes, const int32_t *elem_nodes,
+                   const uint8_t *mask, hpmg_op *out);
+/* Coarse operator on the same elements and the same quadrature points as `fine`,
+ * with basis order Pc - 1 (Pc < fine P).  It reuses the fine operator's geometric
+ * factors and stored linearisation, which makes it the exact Galerkin coarse operator
+ * (Section III-B).  `fine` must outlive it. */
+int hpmg_op_create_coarse(hpmg_op fine, int Pc, int64_t n_nodes, const int32_t *elem_nodes,
+                          const uint8_t *mask, hpmg_op *out);
+void hpmg_op_destroy(hpmg_op op);
+/* Lame parameters: scalars, or per-element device arrays [n_elem] (used when non-NULL;
+ * both must then be given).  Copied to the coarse operators that share the state. */
+int hpmg_op_set_material(hpmg_op op, double mu, double lambda, const double *mu_e,
+                         const double *lambda_e);
+/* Device workspace needed by the operator (tables, geometric factors, stored
+ * linearisation in FP64 and FP32, multiplicities, reduction scratch, flags). */
+int hpmg_op_workspace_bytes(hpmg_op op, size_t *bytes);
+/* Binds a caller-owned device buffer of at least the queried size (256-byte aligned)
+ * and uploads the reference tables; enqueued on `stream`. */
+int hpmg_op_bind_workspace(hpmg_op op, void *workspace, size_t bytes, void *stream);
+/* info[0..7] = P, Q, n_elem, n_nodes, elements per tile, tiles, threads per block,
+ * quadrature-array stride per field. */
+int hpmg_op_info(hpmg_op op, int64_t *info);
+/* Reads and clears the device flag word (synchronises `stream`). */
+int hpmg_op_query_flags(hpmg_op op, void *stream, unsigned *flags);
+
+/* a1: geometric factors (Section II-B: W = w_hat det(dX/dxi), and dxi/dX) from node
+ * coordinates, device double [n_nodes][3] (fine operators only).  Sets
+ * HPMG_FLAG_NONPOSITIVE_J if an element is inverted. */
+int hpmg_qdata_setup(hpmg_op op, const double *coords, void *stream);
+/* Copies the geometric factors out as double [n_elem][10][Q^3] (W, then dxi_k/dX_J
+ * row-major), for inspection and tests. */
+int hpmg_qdata_export(hpmg_op op, double *out, void *stream);
+
+/* a2-a7: residual F(u) of eq. residual-discrete-ref with f_1 = Kirchhoff stress
+ * (eq. Kirchhoff-stress) pulled back to reference coordinates.  u, r: device double
+ * [n_nodes][3].  With store_state != 0 it also stores the 17-scalar linearisation
+ * (dxi/dx, tau, lambda log J, W; Section III-B, Table different-storage) used by
+ * stored-mode Jacobian applies of this operator and its coarse operators. */
+int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void *stream);
+
+/* a5/a5': Jacobian action y = J(u) du (eqs. Jacobian, dtau, Jacobian-discrete-ref).
+ *   precision HPMG_F64: du, y double; HPMG_F32: du, y float (FP32 state and FP32
+ *   accumulation; requires hpmg_state_cast_f32 after the last state update).
+ *   mode HPMG_STORED reads the stored linearisation (u unused, may be NULL);
+ *   HPMG_RECOMPUTE rebuilds it from u (double [n_nodes][3]) and the geometric
+ *   factors (fine operators only, precision HPMG_F64 or HPMG_F32). */
+int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, const void *du,
+                        void *y, void *stream);
+/* Casts the stored FP64 linearisation to the FP32 copy used by FP32 applies. */
+int hpmg_state_cast_f32(hpmg_op op, void *stream);
+
+/* a8: diagonal of this level's Jacobian (stored linearisation, this level's basis on
+ * the shared quadrature), device [n_nodes][3] in `precision`; 1 on constrained rows. */
+int hpmg_diagonal(hpmg_op op, int precision, void *diag, void *stream);
+
+/* a11: p-transfer between a coarse operator and its fine operator (eq. mg_prolong):
+ *   hpmg_prolong_add: yf += M_f P xc   (P = sum_e E_f^T diag(1/m_f) B_ctof E_c)
+ *   hpmg_restrict:    rc  = M_c P^T rf (restriction is the transpose, Section III-B)
+ * Vectors in `precision` (double or float). */
+int hpmg_prolong_add(hpmg_op coarse, hpmg_op fine, int precision, const void *xc, void *yf,
+                     void *stream);
+int hpmg_restrict(hpmg_op fine, hpmg_op coarse, int precision, const void *rf, void *rc,
+                  void *stream);
+
+/* Strain energy Psi(u) = sum W psi (eq. strain-energy) into a device double scalar. */
+int hpmg_energy(hpmg_op op, const double *u, double *psi, void *stream);
+
+/* a16: vector-Jacobian product of the (masked) residual r(u; mu_e, lambda_e):
+ *   u_bar = (dr/du)^T w, written as the transposed pointwise map (adjoint kernel),
+ *   mu_bar[e] = dr/dmu_e^T w, lambda_bar[e] = dr/dlambda_e^T w  (per element).
+ * mode HPMG_STORED uses the linearisation stored by the last hpmg_residual at this u
+ * (parameter gradients then need mu_e, lambda_e > 0); HPMG_RECOMPUTE rebuilds it
+ * from u.  mu_bar / lambda_bar may be NULL.  All double. */
+int hpmg_residual_vjp(hpmg_op op, int mode, const double *u, const double *w, double *u_bar,
+                      double *mu_bar, double *lambda_bar, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * Vector kernels used by the solvers (deterministic FP64 reductions).
+ * n counts scalars.  Reductions write a device double and do not synchronise.
+ * --------------------------------------------------------------------------------- */
+/* scratch: device double buffer of at least HPMG_REDUCE_SCRATCH entries. */
+#define HPMG_REDUCE_SCRATCH 2048
+int hpmg_vec_dot(int precision, int64_t n, const void *x, const void *y, double *out,
+                 double *scratch, void *stream);
+int hpmg_vec_axpby(int precision, int64_t n, double alpha, const void *x, double beta, void *y,
+                   void *stream); /* y = alpha x + beta y */
+int hpmg_vec_cast(int64_t n, int to_precision, const void *x, void *y, void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * p-multigrid preconditioner (Section III-B, Fig. multigrid_algorithm) and solvers.
+ * --------------------------------------------------------------------------------- */
+typedef struct {
+  int cheb_degree;      /* operator applications per smoothing sweep (default 3) */
+  double cheb_lo;       /* interval [lo, hi] * lambda_max (defaults 0.1, 1.1) */
+  double cheb_hi;
+  int lanczos_its;      /* CG/Lanczos iterations for lambda_max (default 10) */
+  double coarse_rtol;   /* coarsest-level Jacobi-PCG relative tolerance (1e-3) */
+  int coarse_maxit;     /* its cap (default 10000) */
+  int coarse_fixed_its; /* > 0: run exactly this many coarse iterations (tests) */
+  int precision;        /* HPMG_F32: smoothing/transfer/coarse solve in FP32 */
+} hpmg_mg_params;
+
+void hpmg_mg_default_params(hpmg_mg_params *p);
+/* levels[0] is the fine operator, levels[l+1] a coarse operator of levels[0] with a
+ * lower order; the last level is solved by Jacobi-PCG.  Handles are borrowed. */
+int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *params,
+                   hpmg_mg *out);
+void hpmg_mg_destroy(hpmg_mg mg);
+int hpmg_mg_workspace_bytes(hpmg_mg mg, size_t *bytes);
+int hpmg_mg_bind_workspace(hpmg_mg mg, void *workspace, size_t bytes);
+/* Per-linearisation setup: FP32 cast of the state (mixed precision), level diagonals
+ * and lambda_max of D^{-1}A per smoothed level from `lanczos_its` Jacobi-PCG
+ * iterations on the caller's rough vectors seeds[l] (device double [n_nodes_l][3],
+ * l = 0 .. n_levels-2).  Synchronises `stream` (reads CG coefficients). */
+int hpmg_mg_setup(hpmg_mg mg, const double *const *seeds, void *stream);
+/* z = M^{-1} r (one V-cycle, zero initial guess), double in and out.
+ * Synchronises once per coarse iteration (convergence test) unless coarse_fixed_its. */
+int hpmg_mg_vcycle(hpmg_mg mg, const double *r, double *z, void *stream);
+/* lambda_max estimate of a level and the last coarse-solve iteration count. */
+int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its);
+
+/* a14: flexible CG (FP64) on the fine operator, preconditioned by one V-cycle of
+ * `mg` (or Jacobi with the fine FP64 diagonal if mg is NULL and diag given).
+ * Solves J x = b from the x passed in; stops at ||b - Jx|| <= rtol ||b - J x0||.
+ * Synchronises once per iteration. */
+int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double rtol, int maxit,
+                   int *its, double *relres, void *stream);
+
+/* a15: Newton with load stepping and the critical-point line search (Section III-A).
+ * Step k = 1..n_steps starts from u + lift / n_steps (lift holds the full imposed
+ * displacement on constrained components and an extension elsewhere) and iterates
+ * until ||F(u)|| <= rtol ||F(u_start)||.  Linear solves: FCG + V-cycle to lin_rtol.
+ * Per-step Newton counts and total Krylov iterations are written to stats (host):
+ *   stats[0] = total Newton iterations, stats[1] = total FCG iterations,
+ *   stats[2] = final relative residual of the last step, stats[3] = failed steps,
+ *   stats[4 + k] = Newton iterations of step k (k < n_steps, at most 60 steps). */
+typedef struct {
+  double rtol;      /* Newton relative residual tolerance (1e-8) */
+  int max_newton;   /* per load step (20) */
+  double lin_rtol;  /* FCG relative tolerance (1e-3) */
+  int lin_maxit;    /* (500) */
+  int line_search;  /* 1: critical-point secant step, clipped to [0.1, 1.5] */
+} hpmg_newton_params;
+void hpmg_newton_default_params(hpmg_newton_params *p);
+int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+                      const hpmg_newton_params *params, const double *const *seeds,
+                      double *stats, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPMG_H */

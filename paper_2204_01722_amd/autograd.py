@@ -1,0 +1,40 @@
+"""The Neo-Hookean residual as a differentiable PyTorch function.
+
+Forward runs the fused residual kernel; backward runs the hand-written adjoint kernel
+(the transpose of the pointwise Jacobian map, scattered through E^T B^T), returning the
+cotangent of the displacement and of the per-element Lame parameters.  In "recompute"
+mode the backward rebuilds the linearisation from the saved displacement instead of
+reading the stored one, trading flops for memory.
+"""
+from __future__ import annotations
+
+import torch
+
+from .binding import Operator
+
+
+class NeoHookeanResidual(torch.autograd.Function):
+    """``r = NeoHookeanResidual.apply(u, mu_e, lam_e, op, mode)``.
+
+    ``u``: float64 [n_nodes][3] on the device; ``mu_e``, ``lam_e``: float64 [n_elem];
+    ``op``: the fine :class:`Operator` (its geometry set up); ``mode``: "stored" or
+    "recompute" (how the backward obtains the linearisation)."""
+
+    @staticmethod
+    def forward(ctx, u, mu_e, lam_e, op: Operator, mode: str = "recompute"):
+        mu_e = mu_e.detach().contiguous()
+        lam_e = lam_e.detach().contiguous()
+        op.set_material(0.0, 0.0, mu_e, lam_e)
+        ud = u.detach().contiguous()
+        r = op.residual(ud, store_state=(mode == "stored"))
+        ctx.op, ctx.mode = op, mode
+        ctx.save_for_backward(ud, mu_e, lam_e)
+        return r
+
+    @staticmethod
+    def backward(ctx, r_bar):
+        u, mu_e, lam_e = ctx.saved_tensors
+        op = ctx.op
+        op.set_material(0.0, 0.0, mu_e, lam_e)
+        ub, mub, lamb = op.residual_vjp(u, r_bar.contiguous().to(torch.float64), mode=ctx.mode)
+        return ub, mub, lamb, None, None

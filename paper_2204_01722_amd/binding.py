@@ -1,0 +1,398 @@
+"""Thin ctypes binding of ``libhpmg.so`` (the C ABI declared in ``include/hpmg.h``).
+
+Argument marshalling only: every computation runs in the library's HIP kernels.  Device
+buffers are PyTorch tensors on the current CUDA (HIP) device; work is enqueued on
+``torch.cuda.current_stream()``.  The module-level ``hpmg_*`` functions mirror the C
+entry points one to one; :class:`Operator` and :class:`PMG` own the handles, the
+workspaces and references to every borrowed tensor.
+
+If the library has not been built, loading fails loudly (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpmg.so")
+
+F64, F32 = 0, 1
+STORED, RECOMPUTE = 0, 1
+FLAG_NONPOSITIVE_J, FLAG_NONFINITE, FLAG_BAD_INDEX = 1, 2, 4
+REDUCE_SCRATCH = 2048
+
+_lib = None
+
+
+class HpmgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"hpmg status {status}: {msg}")
+        self.status = status
+
+
+class MGParams(C.Structure):
+    _fields_ = [("cheb_degree", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
+                ("lanczos_its", C.c_int), ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
+                ("coarse_fixed_its", C.c_int), ("precision", C.c_int)]
+
+
+class NewtonParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_newton", C.c_int), ("lin_rtol", C.c_double),
+                ("lin_maxit", C.c_int), ("line_search", C.c_int)]
+
+
+_VP, _I64, _D, _I = C.c_void_p, C.c_int64, C.c_double, C.c_int
+_SIGS = {
+    "hpmg_status_string": ([_I], C.c_char_p),
+    "hpmg_last_error": ([], C.c_char_p),
+    "hpmg_version": ([], C.c_char_p),
+    "hpmg_basis_tabulate": ([_I, _I, _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "hpmg_basis_ctof": ([_I, _I, _VP], _I),
+    "hpmg_op_create": ([_I, _I, _I64, _I64, _VP, _VP, C.POINTER(_VP)], _I),
+    "hpmg_op_create_coarse": ([_VP, _I, _I64, _VP, _VP, C.POINTER(_VP)], _I),
+    "hpmg_op_destroy": ([_VP], None),
+    "hpmg_op_set_material": ([_VP, _D, _D, _VP, _VP], _I),
+    "hpmg_op_workspace_bytes": ([_VP, C.POINTER(C.c_size_t)], _I),
+    "hpmg_op_bind_workspace": ([_VP, _VP, C.c_size_t, _VP], _I),
+    "hpmg_op_info": ([_VP, _VP], _I),
+    "hpmg_op_query_flags": ([_VP, _VP, C.POINTER(C.c_uint)], _I),
+    "hpmg_qdata_setup": ([_VP, _VP, _VP], _I),
+    "hpmg_qdata_export": ([_VP, _VP, _VP], _I),
+    "hpmg_residual": ([_VP, _VP, _VP, _I, _VP], _I),
+    "hpmg_jacobian_apply": ([_VP, _I, _I, _VP, _VP, _VP, _VP], _I),
+    "hpmg_state_cast_f32": ([_VP, _VP], _I),
+    "hpmg_diagonal": ([_VP, _I, _VP, _VP], _I),
+    "hpmg_prolong_add": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
+    "hpmg_restrict": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
+    "hpmg_energy": ([_VP, _VP, _VP, _VP], _I),
+    "hpmg_residual_vjp": ([_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "hpmg_vec_dot": ([_I, _I64, _VP, _VP, _VP, _VP, _VP], _I),
+    "hpmg_vec_axpby": ([_I, _I64, _D, _VP, _D, _VP, _VP], _I),
+    "hpmg_vec_cast": ([_I64, _I, _VP, _VP, _VP], _I),
+    "hpmg_mg_default_params": ([C.POINTER(MGParams)], None),
+    "hpmg_mg_create": ([_VP, _I, C.POINTER(MGParams), C.POINTER(_VP)], _I),
+    "hpmg_mg_destroy": ([_VP], None),
+    "hpmg_mg_workspace_bytes": ([_VP, C.POINTER(C.c_size_t)], _I),
+    "hpmg_mg_bind_workspace": ([_VP, _VP, C.c_size_t], _I),
+    "hpmg_mg_setup": ([_VP, _VP, _VP], _I),
+    "hpmg_mg_vcycle": ([_VP, _VP, _VP, _VP], _I),
+    "hpmg_mg_info": ([_VP, _I, C.POINTER(_D), C.POINTER(_I)], _I),
+    "hpmg_fcg_solve": ([_VP, _VP, _VP, _VP, _D, _I, C.POINTER(_I), C.POINTER(_D), _VP], _I),
+    "hpmg_newton_default_params": ([C.POINTER(NewtonParams)], None),
+    "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Loads ``libhpmg.so`` once.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2204_01722_amd.build` (no fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != 0:
+        L = lib()
+        raise HpmgError(st, f"{L.hpmg_status_string(st).decode()}: {L.hpmg_last_error().decode()}")
+
+
+def _p(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        if not t.is_cuda:
+            raise ValueError("device tensor expected")
+        if not t.is_contiguous():
+            raise ValueError("contiguous tensor expected")
+        return C.c_void_p(t.data_ptr())
+    return t
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _prec(p):
+    if p in (F64, "f64", "fp64", torch.float64):
+        return F64
+    if p in (F32, "f32", "fp32", torch.float32):
+        return F32
+    raise ValueError(f"bad precision {p!r}")
+
+
+def _mode(m):
+    if m in (STORED, "stored"):
+        return STORED
+    if m in (RECOMPUTE, "recompute"):
+        return RECOMPUTE
+    raise ValueError(f"bad mode {m!r}")
+
+
+def _dtype(prec):
+    return torch.float64 if prec == F64 else torch.float32
+
+
+# ---- host-only entry points --------------------------------------------------------
+def hpmg_basis_tabulate(P: int, Q: int):
+    """Returns dict of numpy arrays: interp [Q][P], grad [Q][P], colloc [Q][Q], qref,
+    qweight [Q], gll [P] (computed by the library on the host)."""
+    import numpy as np
+    out = {k: np.zeros(s) for k, s in (("interp", (Q, P)), ("grad", (Q, P)), ("colloc", (Q, Q)),
+                                        ("qref", (Q,)), ("qweight", (Q,)), ("gll", (P,)))}
+    ptr = {k: v.ctypes.data_as(C.c_void_p) for k, v in out.items()}
+    _check(lib().hpmg_basis_tabulate(P, Q, ptr["interp"], ptr["grad"], ptr["colloc"], ptr["qref"],
+                                     ptr["qweight"], ptr["gll"]))
+    return out
+
+
+def hpmg_basis_ctof(Pf: int, Pc: int):
+    import numpy as np
+    M = np.zeros((Pf, Pc))
+    _check(lib().hpmg_basis_ctof(Pf, Pc, M.ctypes.data_as(C.c_void_p)))
+    return M
+
+
+def hpmg_version() -> str:
+    return lib().hpmg_version().decode()
+
+
+# ---- operator --------------------------------------------------------------------
+class Operator:
+    """One multigrid level: ``E^T B^T D B E`` on one device (handle + workspace)."""
+
+    def __init__(self, P: int, Q: int, elem_nodes: torch.Tensor, n_nodes: int,
+                 mask: torch.Tensor | None = None, fine: "Operator | None" = None):
+        if elem_nodes.dtype != torch.int32:
+            raise ValueError("elem_nodes must be int32")
+        if elem_nodes.dim() != 2 or elem_nodes.shape[1] != P ** 3:
+            raise ValueError("elem_nodes must be [n_elem][P^3]")
+        if mask is not None and (mask.dtype != torch.uint8 or mask.numel() != 3 * n_nodes):
+            raise ValueError("mask must be uint8 [n_nodes][3]")
+        self.P, self.Q, self.n_nodes = P, Q, int(n_nodes)
+        self.n_elem = int(elem_nodes.shape[0])
+        self.device = elem_nodes.device
+        self._keep = [elem_nodes, mask]
+        self.elem_nodes, self.mask, self.fine = elem_nodes, mask, fine
+        h = C.c_void_p()
+        if fine is None:
+            _check(lib().hpmg_op_create(P, Q, self.n_elem, self.n_nodes, _p(elem_nodes), _p(mask),
+                                        C.byref(h)))
+        else:
+            if Q != fine.Q or self.n_elem != fine.n_elem:
+                raise ValueError("a coarse operator shares the fine elements and quadrature")
+            _check(lib().hpmg_op_create_coarse(fine.h, P, self.n_nodes, _p(elem_nodes), _p(mask),
+                                               C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        _check(lib().hpmg_op_workspace_bytes(self.h, C.byref(nb)))
+        self.workspace = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        _check(lib().hpmg_op_bind_workspace(self.h, _p(self.workspace), int(nb.value), _stream()))
+        self._mat = []
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.hpmg_op_destroy(h)
+            self.h = None
+
+    @property
+    def n_dof(self):
+        return 3 * self.n_nodes
+
+    def info(self):
+        arr = (C.c_int64 * 8)()
+        _check(lib().hpmg_op_info(self.h, C.cast(arr, C.c_void_p)))
+        keys = ("P", "Q", "n_elem", "n_nodes", "elems_per_tile", "tiles", "threads", "tile_stride")
+        return dict(zip(keys, list(arr)))
+
+    def set_material(self, mu, lam, mu_e: torch.Tensor | None = None, lam_e: torch.Tensor | None = None):
+        for t in (mu_e, lam_e):
+            if t is not None and (t.dtype != torch.float64 or t.numel() != self.n_elem):
+                raise ValueError("per-element materials must be float64 [n_elem]")
+        self._mat = [mu_e, lam_e]
+        _check(lib().hpmg_op_set_material(self.h, float(mu), float(lam), _p(mu_e), _p(lam_e)))
+
+    def query_flags(self) -> int:
+        f = C.c_uint()
+        _check(lib().hpmg_op_query_flags(self.h, _stream(), C.byref(f)))
+        return int(f.value)
+
+    def _vec(self, dtype=torch.float64):
+        return torch.empty(self.n_nodes, 3, dtype=dtype, device=self.device)
+
+    def _in(self, v, dtype=torch.float64):
+        if v.dtype != dtype or v.numel() != self.n_dof or not v.is_cuda:
+            raise ValueError(f"expected {dtype} device vector with {self.n_dof} entries")
+        return v.contiguous()
+
+    def qdata_setup(self, coords: torch.Tensor):
+        c = self._in(coords)
+        self._keep.append(c)
+        _check(lib().hpmg_qdata_setup(self.h, _p(c), _stream()))
+
+    def qdata_export(self) -> torch.Tensor:
+        out = torch.empty(self.n_elem, 10, self.Q ** 3, dtype=torch.float64, device=self.device)
+        _check(lib().hpmg_qdata_export(self.h, _p(out), _stream()))
+        return out
+
+    def residual(self, u, store_state: bool = True, out=None):
+        u = self._in(u)
+        r = self._vec() if out is None else out
+        _check(lib().hpmg_residual(self.h, _p(u), _p(r), int(bool(store_state)), _stream()))
+        return r
+
+    def jacobian(self, du, precision="f64", mode="stored", u=None, out=None):
+        prec, md = _prec(precision), _mode(mode)
+        du = self._in(du, _dtype(prec))
+        uu = None if u is None else self._in(u)
+        y = self._vec(_dtype(prec)) if out is None else out
+        _check(lib().hpmg_jacobian_apply(self.h, prec, md, _p(uu), _p(du), _p(y), _stream()))
+        return y
+
+    def state_cast_f32(self):
+        _check(lib().hpmg_state_cast_f32(self.h, _stream()))
+
+    def diagonal(self, precision="f64"):
+        prec = _prec(precision)
+        d = self._vec(_dtype(prec))
+        _check(lib().hpmg_diagonal(self.h, prec, _p(d), _stream()))
+        return d
+
+    def energy(self, u) -> torch.Tensor:
+        u = self._in(u)
+        psi = torch.empty((), dtype=torch.float64, device=self.device)
+        _check(lib().hpmg_energy(self.h, _p(u), _p(psi), _stream()))
+        return psi
+
+    def residual_vjp(self, u, w, mode="recompute", want_params=True):
+        u = self._in(u)
+        w = self._in(w)
+        ub = self._vec()
+        mub = lamb = None
+        if want_params:
+            mub = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+            lamb = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
+        _check(lib().hpmg_residual_vjp(self.h, _mode(mode), _p(u), _p(w), _p(ub), _p(mub), _p(lamb),
+                                       _stream()))
+        return ub, mub, lamb
+
+
+def hpmg_prolong_add(coarse: Operator, fine: Operator, xc, yf, precision="f64"):
+    prec = _prec(precision)
+    _check(lib().hpmg_prolong_add(coarse.h, fine.h, prec, _p(xc.contiguous()), _p(yf), _stream()))
+    return yf
+
+
+def hpmg_restrict(fine: Operator, coarse: Operator, rf, precision="f64", out=None):
+    prec = _prec(precision)
+    rc = coarse._vec(_dtype(prec)) if out is None else out
+    _check(lib().hpmg_restrict(fine.h, coarse.h, prec, _p(rf.contiguous()), _p(rc), _stream()))
+    return rc
+
+
+def hpmg_vec_dot(x, y, scratch=None):
+    prec = _prec(x.dtype)
+    if scratch is None:
+        scratch = torch.empty(REDUCE_SCRATCH, dtype=torch.float64, device=x.device)
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(lib().hpmg_vec_dot(prec, x.numel(), _p(x), _p(y), _p(out), _p(scratch), _stream()))
+    return out
+
+
+def hpmg_vec_axpby(alpha, x, beta, y):
+    _check(lib().hpmg_vec_axpby(_prec(x.dtype), x.numel(), float(alpha), _p(x), float(beta), _p(y), _stream()))
+    return y
+
+
+def hpmg_vec_cast(x, dtype):
+    y = torch.empty(x.shape, dtype=dtype, device=x.device)
+    _check(lib().hpmg_vec_cast(x.numel(), _prec(dtype), _p(x), _p(y), _stream()))
+    return y
+
+
+# ---- multigrid -------------------------------------------------------------------
+class PMG:
+    """p-multigrid V-cycle over ``levels`` (fine first), with FCG and Newton drivers."""
+
+    def __init__(self, levels, precision="f64", cheb_degree=3, cheb_lo=0.1, cheb_hi=1.1,
+                 lanczos_its=10, coarse_rtol=1e-3, coarse_maxit=10000, coarse_fixed_its=0):
+        self.levels = list(levels)
+        prm = MGParams()
+        lib().hpmg_mg_default_params(C.byref(prm))
+        prm.cheb_degree, prm.cheb_lo, prm.cheb_hi = cheb_degree, cheb_lo, cheb_hi
+        prm.lanczos_its, prm.coarse_rtol, prm.coarse_maxit = lanczos_its, coarse_rtol, coarse_maxit
+        prm.coarse_fixed_its, prm.precision = coarse_fixed_its, _prec(precision)
+        self.params = prm
+        arr = (C.c_void_p * len(self.levels))(*[op.h.value for op in self.levels])
+        h = C.c_void_p()
+        _check(lib().hpmg_mg_create(C.cast(arr, C.c_void_p), len(self.levels), C.byref(prm), C.byref(h)))
+        self.h = h
+        nb = C.c_size_t()
+        _check(lib().hpmg_mg_workspace_bytes(self.h, C.byref(nb)))
+        dev = self.levels[0].device
+        self.workspace = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=dev)
+        _check(lib().hpmg_mg_bind_workspace(self.h, _p(self.workspace), int(nb.value)))
+        self._seeds = None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.hpmg_mg_destroy(h)
+            self.h = None
+
+    def _seed_array(self, seeds):
+        seeds = [s.contiguous() for s in seeds]
+        if len(seeds) < len(self.levels) - 1:
+            raise ValueError("one rough seed vector per smoothed level")
+        self._seeds = seeds
+        arr = (C.c_void_p * len(seeds))(*[s.data_ptr() for s in seeds])
+        self._seed_c = arr
+        return C.cast(arr, C.c_void_p)
+
+    def setup(self, seeds):
+        _check(lib().hpmg_mg_setup(self.h, self._seed_array(seeds), _stream()))
+
+    def vcycle(self, r):
+        z = torch.empty_like(r)
+        _check(lib().hpmg_mg_vcycle(self.h, _p(r.contiguous()), _p(z), _stream()))
+        return z
+
+    def info(self, level):
+        lam, its = C.c_double(), C.c_int()
+        _check(lib().hpmg_mg_info(self.h, level, C.byref(lam), C.byref(its)))
+        return float(lam.value), int(its.value)
+
+    def fcg(self, b, x=None, rtol=1e-8, maxit=500):
+        x = torch.zeros_like(b) if x is None else x
+        its, rel = C.c_int(), C.c_double()
+        _check(lib().hpmg_fcg_solve(self.levels[0].h, self.h, _p(b.contiguous()), _p(x), float(rtol),
+                                    int(maxit), C.byref(its), C.byref(rel), _stream()))
+        return x, int(its.value), float(rel.value)
+
+    def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
+               line_search=True):
+        prm = NewtonParams()
+        lib().hpmg_newton_default_params(C.byref(prm))
+        prm.rtol, prm.max_newton, prm.lin_rtol = rtol, max_newton, lin_rtol
+        prm.lin_maxit, prm.line_search = lin_maxit, int(bool(line_search))
+        stats = (C.c_double * (4 + n_steps))()
+        st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()), int(n_steps),
+                                     C.byref(prm), self._seed_array(seeds), C.cast(stats, C.c_void_p),
+                                     _stream())
+        s = list(stats)
+        res = {"newton_its": int(s[0]), "krylov_its": int(s[1]), "final_rel": s[2], "failed_steps": int(s[3]),
+               "per_step": [int(v) for v in s[4:]]}
+        _check(st)
+        return u, res

@@ -1,0 +1,142 @@
+// Internal declarations shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/hpmg.h"
+
+namespace hpmg {
+
+// ---------------------------------------------------------------------------------
+// Quadrature tiling.  Quadrature-point arrays (geometric factors, stored
+// linearisation) are laid out [tile][field][ET * Q^3]: the ET consecutive elements of
+// a tile are processed by one workgroup with one thread per quadrature point, so each
+// field is read by one contiguous, fully coalesced sweep of the workgroup.
+// ---------------------------------------------------------------------------------
+constexpr int elems_per_tile(int Q) {
+  return Q == 2 ? 32 : Q == 3 ? 9 : Q == 4 ? 4 : Q == 5 ? 2 : 1;
+}
+constexpr int tile_threads(int Q) {
+  return ((elems_per_tile(Q) * Q * Q * Q + 63) / 64) * 64;
+}
+
+constexpr int NGEO = 10;    // W, dxi_k/dX_J (row-major)
+constexpr int NSTATE = 17;  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
+
+// Reference tables, in the operator's precision, at fixed offsets (max 8 x 8 each).
+constexpr int TAB_B = 0;      // [Q][P] interpolation
+constexpr int TAB_G = 64;     // [Q][P] reference derivative
+constexpr int TAB_D = 128;    // [Q][Q] collocated derivative
+constexpr int TAB_W = 192;    // [Q]    1D Gauss weights
+constexpr int TAB_BB = 200;   // [Q][P] B*B   (elementwise, diagonal assembly)
+constexpr int TAB_BG = 264;   // [Q][P] B*G
+constexpr int TAB_GG = 328;   // [Q][P] G*G
+constexpr int TAB_CTOF = 392; // [Pf][P] interpolation from this order to order Pf - 1,
+                              // slot (Pf - 2) of 64 values, Pf = P+1 .. 6
+constexpr int TAB_SIZE = 392 + 5 * 64;
+__host__ __device__ constexpr int tab_ctof(int Pf) { return TAB_CTOF + (Pf - 2) * 64; }
+
+// Element-to-node map used by the kernels: node id in the low 28 bits, the Dirichlet
+// flags of the node's three components in bits 28..30.
+constexpr uint32_t EMAP_ID_MASK = (1u << 28) - 1u;
+constexpr int EMAP_BC_SHIFT = 28;
+constexpr int64_t MAX_NODES = int64_t(1) << 28;
+
+constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
+
+}  // namespace hpmg
+
+struct hpmg_op_s {
+  int P = 0, Q = 0;
+  int64_t E = 0, N = 0;
+  const int32_t *elem_nodes = nullptr;
+  const uint8_t *mask = nullptr;
+  hpmg_op_s *fine = nullptr;  // non-null for coarse operators
+  double mu = 0.0, lam = 0.0;
+  const double *mu_e = nullptr, *lam_e = nullptr;
+  int ET = 0, NQ = 0, NT = 0;
+  int64_t tiles = 0;
+  // workspace carve-up
+  char *ws = nullptr;
+  size_t ws_bytes = 0;
+  double *tab64 = nullptr;
+  float *tab32 = nullptr;
+  uint32_t *emap = nullptr;
+  double *geo = nullptr;       // fine only
+  double *state64 = nullptr;   // fine only
+  float *state32 = nullptr;    // fine only
+  double *invmult64 = nullptr; // 1 / (number of elements sharing the node)
+  float *invmult32 = nullptr;
+  double *scratch = nullptr;   // reductions
+  unsigned *flags = nullptr;
+  bool geo_ready = false, state_ready = false, state32_ready = false;
+  void *host_extra = nullptr;  // host-side tables and scalars owned by the handle
+};
+
+namespace hpmg {
+
+// Error reporting (thread-local message).
+int fail(int status, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+#define HPMG_HIP(call)                                     \
+  do {                                                     \
+    hipError_t _e = (call);                                \
+    if (_e != hipSuccess) return ::hpmg::hip_fail(_e, #call); \
+  } while (0)
+
+// Host tabulation (basis.cpp).
+int tabulate(int P, int Q, double *B, double *G, double *D, double *xq, double *wq, double *gll);
+int ctof_table(int Pf, int Pc, double *M);
+
+// Launchers (op_kernels.hip / vec_kernels.hip).  All return hipError_t of the launch.
+bool supported_pq(int P, int Q);
+hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
+hipError_t launch_multiplicity(const hpmg_op_s &op, hipStream_t s);
+hipError_t launch_qdata(const hpmg_op_s &op, const double *coords, hipStream_t s);
+hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s);
+hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,
+                           void *y, hipStream_t s);
+hipError_t launch_diagonal(const hpmg_op_s &op, int prec, void *diag, hipStream_t s);
+hipError_t launch_prolong_add(const hpmg_op_s &coarse, const hpmg_op_s &fine, int prec,
+                              const void *xc, void *yf, hipStream_t s);
+hipError_t launch_restrict(const hpmg_op_s &fine, const hpmg_op_s &coarse, int prec, const void *rf,
+                           void *rc, hipStream_t s);
+hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipStream_t s);
+hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
+                      double *mub, double *lamb, hipStream_t s);
+hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s);
+
+// Vector kernels.
+hipError_t launch_init_bc(int prec, int64_t n_nodes, const uint8_t *mask, const void *x, void *y,
+                          hipStream_t s);  // y = mask ? x : 0
+hipError_t launch_fill_bc_one(int prec, int64_t n_nodes, const uint8_t *mask, void *y, hipStream_t s);
+hipError_t launch_cast_state(int64_t n, const double *a, float *b, hipStream_t s);
+hipError_t launch_dot(int prec, int64_t n, const void *x, const void *y, double *partial,
+                      double *out, hipStream_t s);
+hipError_t launch_dot2(int prec, int64_t n, const void *x, const void *y, const void *z,
+                       double *partial, double *out, hipStream_t s);  // out[0]=x.y, out[1]=z.z
+hipError_t launch_sum(int64_t n, const double *x, double *partial, double *out, hipStream_t s);
+hipError_t launch_axpby(int prec, int64_t n, double a, const void *x, double b, void *y, hipStream_t s);
+hipError_t launch_waxpby(int prec, int64_t n, double a, const void *x, double b, const void *y,
+                         void *w, hipStream_t s);  // w = a x + b y
+hipError_t launch_cg_update(int prec, int64_t n, double alpha, const void *p, const void *q, void *x,
+                            const void *r_in, void *r_out, hipStream_t s);  // x += a p; r_out = r_in - a q
+hipError_t launch_jacobi_dot(int prec, int64_t n, const void *dinv, const void *r, void *z,
+                             double *partial, double *out, hipStream_t s);  // z = dinv r; out = {r.z, r.r}
+hipError_t launch_dot_pair(int prec, int64_t n, const void *z, const void *a, const void *b,
+                           double *partial, double *out, hipStream_t s);  // out = {z.a, z.b}
+hipError_t launch_cast(int64_t n, int to_prec, const void *x, void *y, hipStream_t s);
+hipError_t launch_mul(int prec, int64_t n, const void *a, const void *x, void *y, hipStream_t s);
+hipError_t launch_recip(int prec, int64_t n, void *x, hipStream_t s);
+hipError_t launch_cheb_first(int prec, int64_t n, const void *dinv, const void *b, const void *Ax,
+                             void *r, void *d, void *x, double inv_theta, hipStream_t s);
+hipError_t launch_cheb_step(int prec, int64_t n, const void *dinv, void *r, const void *Ad, void *d,
+                            void *x, double c1, double c2, hipStream_t s);
+
+size_t prec_size(int prec);
+
+}  // namespace hpmg

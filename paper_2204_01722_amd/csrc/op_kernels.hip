@@ -1,0 +1,1137 @@
+// Fused element kernels of the matrix-free Neo-Hookean operator for gfx950.
+//
+// One workgroup processes one tile of ET consecutive elements with one thread per
+// quadrature point (Q^3 per element).  Inside a kernel the element vector and the
+// quadrature vector never leave the chip (Fig. libceedapi caption: E, B and D fused):
+//
+//   gather (E)  ->  sum-factorised interpolation, three 1D contractions staged in LDS
+//   ->  collocated derivative B_xi B_I^+ (three more contractions, Section II-B)
+//   ->  pointwise constitutive map in registers (Section II-A)
+//   ->  transposed derivative and interpolation in LDS  ->  atomic scatter-add (E^T).
+//
+// Quadrature-point data are read/written as [tile][field][ET*Q^3] so each field of a
+// tile is one contiguous, coalesced sweep.  Dirichlet flags ride in the top bits of the
+// element-to-node map, so masking costs no extra memory traffic.
+#include <cmath>
+
+#include "common.h"
+
+namespace hpmg {
+namespace {
+
+template <int Q>
+struct QT {
+  static constexpr int Q3 = Q * Q * Q;
+  static constexpr int ET = elems_per_tile(Q);
+  static constexpr int NQ = ET * Q3;
+  static constexpr int NT = tile_threads(Q);
+};
+
+__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// One 1D contraction along direction DIR of an array with dims (N1, N2, N3), N1
+// fastest, for NC components stored back to back.  Output dims replace N_DIR by NO.
+// TR = false: out_o = sum_i M[o][i] in_i (M is [NO][NI]);
+// TR = true:  out_o = sum_i M[i][o] in_i (M is [NI][NO], the transpose is applied).
+template <typename T, int N1, int N2, int N3, int DIR, int NO, bool TR, int NC>
+__device__ __forceinline__ void stage(const T *__restrict__ in, T *__restrict__ out,
+                                      const T *__restrict__ M, int q, bool live) {
+  constexpr int NI = DIR == 0 ? N1 : DIR == 1 ? N2 : N3;
+  constexpr int O1 = DIR == 0 ? NO : N1, O2 = DIR == 1 ? NO : N2, O3 = DIR == 2 ? NO : N3;
+  constexpr int NIN = N1 * N2 * N3, NOUT = O1 * O2 * O3;
+  constexpr int STR = DIR == 0 ? 1 : DIR == 1 ? N1 : N1 * N2;
+  if (live && q < NOUT) {
+    const int o1 = q % O1, o2 = (q / O1) % O2, o3 = q / (O1 * O2);
+    const int o = DIR == 0 ? o1 : DIR == 1 ? o2 : o3;
+    const int base = (DIR == 0 ? 0 : o1) + N1 * ((DIR == 1 ? 0 : o2) + N2 * (DIR == 2 ? 0 : o3));
+    T m[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) m[i] = TR ? M[i * NO + o] : M[o * NI + i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      T acc = 0;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) acc += m[i] * in[c * NIN + base + i * STR];
+      out[c * NOUT + q] = acc;
+    }
+  }
+}
+
+// Nodes [NC][P^3] in `a` -> quadrature values [NC][Q^3] in `b` (a is overwritten).
+template <typename T, int P, int Q, int NC>
+__device__ __forceinline__ void interp(T *a, T *b, const T *sB, int q, bool live) {
+  stage<T, P, P, P, 0, Q, false, NC>(a, b, sB, q, live);
+  __syncthreads();
+  stage<T, Q, P, P, 1, Q, false, NC>(b, a, sB, q, live);
+  __syncthreads();
+  stage<T, Q, Q, P, 2, Q, false, NC>(a, b, sB, q, live);
+  __syncthreads();
+}
+
+// Quadrature values [NC][Q^3] in `b` -> nodes [NC][P^3] in `a` (transpose of interp).
+template <typename T, int P, int Q, int NC>
+__device__ __forceinline__ void interp_t(T *b, T *a, const T *sB, int q, bool live) {
+  stage<T, Q, Q, Q, 2, P, true, NC>(b, a, sB, q, live);
+  __syncthreads();
+  stage<T, Q, Q, P, 1, P, true, NC>(a, b, sB, q, live);
+  __syncthreads();
+  stage<T, Q, P, P, 0, P, true, NC>(b, a, sB, q, live);
+  __syncthreads();
+}
+
+// Reference gradient at quadrature point q from quadrature values (collocated
+// derivative): G[c][k] = d(component c)/d xi_k.
+template <typename T, int Q, int NC>
+__device__ __forceinline__ void grad_q(const T *in, const T *sD, int q, T (&G)[NC][3]) {
+  constexpr int Q3 = Q * Q * Q;
+  const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) G[c][0] = G[c][1] = G[c][2] = 0;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    const T d1 = sD[q1 * Q + j], d2 = sD[q2 * Q + j], d3 = sD[q3 * Q + j];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      G[c][0] += d1 * in[c * Q3 + j + Q * (q2 + Q * q3)];
+      G[c][1] += d2 * in[c * Q3 + q1 + Q * (j + Q * q3)];
+      G[c][2] += d3 * in[c * Q3 + q1 + Q * (q2 + Q * j)];
+    }
+  }
+}
+
+// Transposed collocated derivative summed over directions: out[c][q] =
+// sum_k sum_j D[j][q_k] f[c][k][.. j ..], f laid out [3][3][Q^3].
+template <typename T, int Q>
+__device__ __forceinline__ void grad_t_q(const T *f, const T *sD, int q, T *out, bool live) {
+  constexpr int Q3 = Q * Q * Q;
+  if (!live || q >= Q3) return;
+  const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      acc += sD[j * Q + q1] * f[(c * 3 + 0) * Q3 + j + Q * (q2 + Q * q3)];
+      acc += sD[j * Q + q2] * f[(c * 3 + 1) * Q3 + q1 + Q * (j + Q * q3)];
+      acc += sD[j * Q + q3] * f[(c * 3 + 2) * Q3 + q1 + Q * (q2 + Q * j)];
+    }
+    out[c * Q3 + q] = acc;
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T det3(const T (&m)[3][3]) {
+  return m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+         m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+         m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+}
+
+// adj(m) / det  (inverse), given det.
+template <typename T>
+__device__ __forceinline__ void inv3(const T (&m)[3][3], T det, T (&r)[3][3]) {
+  const T id = T(1) / det;
+  r[0][0] = (m[1][1] * m[2][2] - m[1][2] * m[2][1]) * id;
+  r[0][1] = (m[0][2] * m[2][1] - m[0][1] * m[2][2]) * id;
+  r[0][2] = (m[0][1] * m[1][2] - m[0][2] * m[1][1]) * id;
+  r[1][0] = (m[1][2] * m[2][0] - m[1][0] * m[2][2]) * id;
+  r[1][1] = (m[0][0] * m[2][2] - m[0][2] * m[2][0]) * id;
+  r[1][2] = (m[0][2] * m[1][0] - m[0][0] * m[1][2]) * id;
+  r[2][0] = (m[1][0] * m[2][1] - m[1][1] * m[2][0]) * id;
+  r[2][1] = (m[0][1] * m[2][0] - m[0][0] * m[2][1]) * id;
+  r[2][2] = (m[0][0] * m[1][1] - m[0][1] * m[1][0]) * id;
+}
+
+// Symmetric tau stored as (xx, yy, zz, yz, xz, xy).
+__device__ __forceinline__ constexpr int sym_index(int i, int j) {
+  return i == j ? i : (i + j == 1 ? 5 : (i + j == 2 ? 4 : 3));
+}
+
+// Kinematics and Kirchhoff stress from the reference gradient G = du/dxi and the
+// inverse geometric Jacobian D = dxi/dX (Section II-A):
+//   H = G D, J - 1 = tr H + ((tr H)^2 - tr H^2)/2 + det H (no cancellation),
+//   log J = log1p(J - 1), tau = mu (H + H^T + H H^T) + lambda log J I,
+//   A = dxi/dx = D F^{-1}.
+// J - 1 and log J are always evaluated in double.
+template <typename T>
+struct Kin {
+  T A[3][3];
+  T tau[6];
+  T c;       // lambda log J
+  double logJ;
+  double Jm1;
+  T H[3][3];
+};
+
+template <typename T>
+__device__ __forceinline__ void kinematics(const T (&G)[3][3], const T (&D)[3][3], T mu, T lam,
+                                           Kin<T> &k) {
+  for (int i = 0; i < 3; ++i)
+    for (int J = 0; J < 3; ++J) k.H[i][J] = G[i][0] * D[0][J] + G[i][1] * D[1][J] + G[i][2] * D[2][J];
+  double Hd[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Hd[i][j] = (double)k.H[i][j];
+  const double tr = Hd[0][0] + Hd[1][1] + Hd[2][2];
+  double tr2 = 0.0;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) tr2 += Hd[i][j] * Hd[j][i];
+  k.Jm1 = tr + 0.5 * (tr * tr - tr2) + det3(Hd);
+  k.logJ = log1p(k.Jm1);
+  k.c = lam * (T)k.logJ;
+  for (int i = 0; i < 3; ++i)
+    for (int j = i; j < 3; ++j) {
+      T b = k.H[i][0] * k.H[j][0] + k.H[i][1] * k.H[j][1] + k.H[i][2] * k.H[j][2];
+      T t = mu * (k.H[i][j] + k.H[j][i] + b);
+      if (i == j) t += k.c;
+      k.tau[sym_index(i, j)] = t;
+    }
+  T F[3][3], Fi[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) F[i][j] = (i == j ? T(1) : T(0)) + k.H[i][j];
+  inv3(F, (T)(1.0 + k.Jm1), Fi);
+  for (int a = 0; a < 3; ++a)
+    for (int j = 0; j < 3; ++j) k.A[a][j] = D[a][0] * Fi[0][j] + D[a][1] * Fi[1][j] + D[a][2] * Fi[2][j];
+}
+
+// Residual pointwise map: f[i][k] = W sum_j tau_ij A_kj  (W tau (dxi/dx)^T).
+template <typename T>
+__device__ __forceinline__ void residual_qf(const Kin<T> &k, T W, T (&f)[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) {
+      T s = 0;
+      for (int j = 0; j < 3; ++j) s += k.tau[sym_index(i, j)] * k.A[a][j];
+      f[i][a] = W * s;
+    }
+}
+
+// Jacobian pointwise map (eqs. Jacobian, dtau, depsilon in current configuration):
+//   g = G A = grad_x du;  s = g tau + lambda tr(g) I + (mu - lambda log J)(g + g^T);
+//   f = W s A^T.
+template <typename T>
+__device__ __forceinline__ void jacobian_qf(const T (&G)[3][3], const T (&A)[3][3], const T (&tau)[6],
+                                            T c, T W, T mu, T lam, T (&f)[3][3]) {
+  T g[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) g[i][j] = G[i][0] * A[0][j] + G[i][1] * A[1][j] + G[i][2] * A[2][j];
+  const T trg = g[0][0] + g[1][1] + g[2][2];
+  const T m2 = mu - c;
+  T s[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      T v = g[i][0] * tau[sym_index(0, j)] + g[i][1] * tau[sym_index(1, j)] + g[i][2] * tau[sym_index(2, j)];
+      v += m2 * (g[i][j] + g[j][i]);
+      if (i == j) v += lam * trg;
+      s[i][j] = v;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) f[i][a] = W * (s[i][0] * A[a][0] + s[i][1] * A[a][1] + s[i][2] * A[a][2]);
+}
+
+// Adjoint pointwise map, written as the transpose of jacobian_qf: for a cotangent
+// C = dw/dxi, s*(M) = M tau^T + lambda tr(M) I + (mu - c)(M + M^T) with M = C A, and
+// f = W s*(M) A^T.
+template <typename T>
+__device__ __forceinline__ void adjoint_qf(const T (&C)[3][3], const T (&A)[3][3], const T (&tau)[6],
+                                           T c, T W, T mu, T lam, T (&f)[3][3], T (&M)[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i][j] = C[i][0] * A[0][j] + C[i][1] * A[1][j] + C[i][2] * A[2][j];
+  const T trM = M[0][0] + M[1][1] + M[2][2];
+  const T m2 = mu - c;
+  T s[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      // (M tau^T)_ij = sum_m M_im tau_jm
+      T v = M[i][0] * tau[sym_index(j, 0)] + M[i][1] * tau[sym_index(j, 1)] + M[i][2] * tau[sym_index(j, 2)];
+      v += m2 * (M[i][j] + M[j][i]);
+      if (i == j) v += lam * trM;
+      s[i][j] = v;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int a = 0; a < 3; ++a) f[i][a] = W * (s[i][0] * A[a][0] + s[i][1] * A[a][1] + s[i][2] * A[a][2]);
+}
+
+__device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
+  return mu_e ? mu_e[e] : mu0;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_tables(T *dst, const T *__restrict__ src, int off, int n, int t, int nt) {
+  for (int i = t; i < n; i += nt) dst[i] = src[off + i];
+}
+
+// ------------------------------------------------------------------------------------
+// a1: geometric factors.
+// ------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict__ emap,
+                                                     const double *__restrict__ X,
+                                                     const double *__restrict__ tab,
+                                                     double *__restrict__ geo,
+                                                     unsigned *__restrict__ flags, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 3 * Q3, S1 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q], sW[Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  load_tables(sW, tab, TAB_W, Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  if (live && q < P3) {
+    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c * P3 + q] = X[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  interp<T, P, Q, 3>(a, b, sB, q, live);
+  T G[3][3];
+  if (live) grad_q<T, Q, 3>(b, sD, q, G);
+  if (!live) return;
+  const T det = det3(G);
+  if (!(det > 0.0)) atomicOr(flags, det == det ? HPMG_FLAG_NONPOSITIVE_J : HPMG_FLAG_NONFINITE);
+  T Di[3][3];
+  inv3(G, det, Di);  // Di[k][J] = dxi_k / dX_J
+  const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+  double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+  g[0] = sW[q1] * sW[q2] * sW[q3] * det;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) g[(1 + k * 3 + J) * NQ] = Di[k][J];
+}
+
+// ------------------------------------------------------------------------------------
+// a2-a7: residual (FP64), optionally storing the 17-scalar linearisation.
+// ------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_residual(
+    const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ geo,
+    const double *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
+    const double *__restrict__ lam_e, double *__restrict__ r, double *__restrict__ state,
+    unsigned *__restrict__ flags, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  if (live && q < P3) {
+    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c * P3 + q] = u[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  interp<T, P, Q, 3>(a, b, sB, q, live);
+  if (live) {
+    T G[3][3], D[3][3];
+    grad_q<T, Q, 3>(b, sD, q, G);
+    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+    const T W = g[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+    const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
+    Kin<T> k;
+    kinematics(G, D, mu, lam, k);
+    if (!(k.Jm1 > -1.0)) atomicOr(flags, k.Jm1 == k.Jm1 ? HPMG_FLAG_NONPOSITIVE_J : HPMG_FLAG_NONFINITE);
+    T f[3][3];
+    residual_qf(k, W, f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
+    if (state) {
+      double *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s[(kk * 3 + j) * NQ] = k.A[kk][j];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) s[(9 + m) * NQ] = k.tau[m];
+      s[15 * NQ] = k.c;
+      s[16 * NQ] = W;
+    }
+  }
+  __syncthreads();
+  grad_t_q<T, Q>(a, sD, q, b, live);
+  __syncthreads();
+  interp_t<T, P, Q, 3>(b, a, sB, q, live);
+  if (live && q < P3) {
+    const uint32_t w = emap[e * P3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&r[(int64_t)node * 3 + c], a[c * P3 + q]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// a5: Jacobian action from the stored linearisation (FP64 or FP32).
+// ------------------------------------------------------------------------------------
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
+    const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
+    const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
+    const double *__restrict__ lam_e, T *__restrict__ y, int64_t E) {
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  uint32_t w = 0;
+  if (live && q < P3) {
+    w = emap[e * P3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      a[c * P3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : du[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  interp<T, P, Q, 3>(a, b, sB, q, live);
+  if (live) {
+    T G[3][3], A[3][3], tau[6];
+    grad_q<T, Q, 3>(b, sD, q, G);
+    const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[k][j] = s[(k * 3 + j) * NQ];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
+    const T c = s[15 * NQ], W = s[16 * NQ];
+    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+    T f[3][3];
+    jacobian_qf(G, A, tau, c, W, mu, lam, f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a[(i * 3 + k) * Q3 + q] = f[i][k];
+  }
+  __syncthreads();
+  grad_t_q<T, Q>(a, sD, q, b, live);
+  __syncthreads();
+  interp_t<T, P, Q, 3>(b, a, sB, q, live);
+  if (live && q < P3) {
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&y[(int64_t)node * 3 + c], a[c * P3 + q]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// a5': Jacobian action recomputing the linearisation from u and the geometry.
+// ------------------------------------------------------------------------------------
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
+    const uint32_t *__restrict__ emap, const double *__restrict__ u, const T *__restrict__ du,
+    const double *__restrict__ geo, const T *__restrict__ tab, double mu0, double lam0,
+    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ y, int64_t E) {
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  uint32_t w = 0;
+  if (live && q < P3) {
+    w = emap[e * P3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a[c * P3 + q] = (T)u[(int64_t)node * 3 + c];
+      a[(3 + c) * P3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : du[(int64_t)node * 3 + c];
+    }
+  }
+  __syncthreads();
+  interp<T, P, Q, 6>(a, b, sB, q, live);
+  if (live) {
+    T G6[6][3], Gu[3][3], Gd[3][3], D[3][3];
+    grad_q<T, Q, 6>(b, sD, q, G6);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        Gu[i][k] = G6[i][k];
+        Gd[i][k] = G6[3 + i][k];
+      }
+    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+    const T W = (T)g[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) D[k][J] = (T)g[(1 + k * 3 + J) * NQ];
+    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+    Kin<T> k;
+    kinematics(Gu, D, mu, lam, k);
+    T f[3][3];
+    jacobian_qf(Gd, k.A, k.tau, k.c, W, mu, lam, f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
+  }
+  __syncthreads();
+  grad_t_q<T, Q>(a, sD, q, b, live);
+  __syncthreads();
+  interp_t<T, P, Q, 3>(b, a, sB, q, live);
+  if (live && q < P3) {
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&y[(int64_t)node * 3 + c], a[c * P3 + q]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// a8: diagonal.  Per quadrature point and component i, the 3x3 block
+//   K^(i)_kl = W [ (A tau A^T)_kl + (mu - c)(A A^T)_kl + (lambda + mu - c) A_ki A_li ]
+// (the Jacobian map with G = e_i grad(phi)^T); the node value is
+//   sum_q sum_kl K^(i)_kl dphi/dxi_k dphi/dxi_l,
+// a tensor product of the 1D elementwise tables B*B, B*G, G*G, contracted in three
+// transposed 1D stages for each of the six (k, l) pairs.
+// ------------------------------------------------------------------------------------
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
+    const uint32_t *__restrict__ emap, const T *__restrict__ state, const T *__restrict__ tab,
+    double mu0, double lam0, const double *__restrict__ mu_e, const double *__restrict__ lam_e,
+    T *__restrict__ diag, int64_t E) {
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 3 * Q3, S1 = 3 * Q3;
+  __shared__ T sBB[Q * P], sBG[Q * P], sGG[Q * P];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sBB, tab, TAB_BB, Q * P, tq, NT);
+  load_tables(sBG, tab, TAB_BG, Q * P, tq, NT);
+  load_tables(sGG, tab, TAB_GG, Q * P, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  T K[3][6];  // [component][pair]
+  if (live) {
+    T A[3][3], tau[6];
+    const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[k][j] = s[(k * 3 + j) * NQ];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
+    const T c = s[15 * NQ], W = s[16 * NQ];
+    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+    T AT[3][3];  // (A tau)
+    for (int k = 0; k < 3; ++k)
+      for (int j = 0; j < 3; ++j)
+        AT[k][j] = A[k][0] * tau[sym_index(0, j)] + A[k][1] * tau[sym_index(1, j)] + A[k][2] * tau[sym_index(2, j)];
+    const int pk[6] = {0, 1, 2, 1, 0, 0}, pl[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+    for (int p = 0; p < 6; ++p) {
+      const int k = pk[p], l = pl[p];
+      const T m1 = AT[k][0] * A[l][0] + AT[k][1] * A[l][1] + AT[k][2] * A[l][2];
+      const T m2 = A[k][0] * A[l][0] + A[k][1] * A[l][1] + A[k][2] * A[l][2];
+      const T sc = (k == l) ? W : T(2) * W;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) K[i][p] = sc * (m1 + (mu - c) * m2 + (lam + mu - c) * A[k][i] * A[l][i]);
+    }
+  }
+  T acc[3] = {0, 0, 0};
+  const int pk[6] = {0, 1, 2, 1, 0, 0}, pl[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+  for (int p = 0; p < 6; ++p) {
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) b[i * Q3 + q] = K[i][p];
+    }
+    __syncthreads();
+    const int k = pk[p], l = pl[p];
+    const T *t1 = (k == 0 && l == 0) ? sGG : (k == 0 || l == 0) ? sBG : sBB;
+    const T *t2 = (k == 1 && l == 1) ? sGG : (k == 1 || l == 1) ? sBG : sBB;
+    const T *t3 = (k == 2 && l == 2) ? sGG : (k == 2 || l == 2) ? sBG : sBB;
+    stage<T, Q, Q, Q, 2, P, true, 3>(b, a, t3, q, live);
+    __syncthreads();
+    stage<T, Q, Q, P, 1, P, true, 3>(a, b, t2, q, live);
+    __syncthreads();
+    stage<T, Q, P, P, 0, P, true, 3>(b, a, t1, q, live);
+    __syncthreads();
+    if (live && q < P3) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) acc[i] += a[i * P3 + q];
+    }
+  }
+  if (live && q < P3) {
+    const uint32_t w = emap[e * P3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&diag[(int64_t)node * 3 + c], acc[c]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// a11: p-transfer on the same elements (eq. mg_prolong).
+// ------------------------------------------------------------------------------------
+template <typename T, int PF, int PC>
+__global__ __launch_bounds__(QT<PF>::NT) void k_prolong_add(
+    const uint32_t *__restrict__ emap_c, const uint32_t *__restrict__ emap_f, const T *__restrict__ xc,
+    const T *__restrict__ invm, const T *__restrict__ tab_c, T *__restrict__ yf, int64_t E) {
+  constexpr int F3 = PF * PF * PF, C3 = PC * PC * PC, ET = QT<PF>::ET, NQ = ET * F3, NT = QT<PF>::NT;
+  constexpr int S = 3 * F3;
+  __shared__ T sM[PF * PC];
+  __shared__ T lds[2 * ET * S];
+  const int tq = threadIdx.x, el = tq / F3, q = tq % F3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sM, tab_c, tab_ctof(PF), PF * PC, tq, NT);
+  T *a = lds + (live ? el : 0) * S, *b = lds + ET * S + (live ? el : 0) * S;
+  if (live && q < C3) {
+    const uint32_t w = emap_c[e * C3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      a[c * C3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : xc[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  stage<T, PC, PC, PC, 0, PF, false, 3>(a, b, sM, q, live);
+  __syncthreads();
+  stage<T, PF, PC, PC, 1, PF, false, 3>(b, a, sM, q, live);
+  __syncthreads();
+  stage<T, PF, PF, PC, 2, PF, false, 3>(a, b, sM, q, live);
+  __syncthreads();
+  if (live) {
+    const uint32_t w = emap_f[e * F3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+    const T s = invm[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&yf[(int64_t)node * 3 + c], s * b[c * F3 + q]);
+  }
+}
+
+template <typename T, int PF, int PC>
+__global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
+    const uint32_t *__restrict__ emap_f, const uint32_t *__restrict__ emap_c, const T *__restrict__ rf,
+    const T *__restrict__ invm, const T *__restrict__ tab_c, T *__restrict__ rc, int64_t E) {
+  constexpr int F3 = PF * PF * PF, C3 = PC * PC * PC, ET = QT<PF>::ET, NQ = ET * F3, NT = QT<PF>::NT;
+  constexpr int S = 3 * F3;
+  __shared__ T sM[PF * PC];
+  __shared__ T lds[2 * ET * S];
+  const int tq = threadIdx.x, el = tq / F3, q = tq % F3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sM, tab_c, tab_ctof(PF), PF * PC, tq, NT);
+  T *a = lds + (live ? el : 0) * S, *b = lds + ET * S + (live ? el : 0) * S;
+  if (live) {
+    const uint32_t w = emap_f[e * F3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+    const T s = invm[node];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      a[c * F3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : s * rf[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  stage<T, PF, PF, PF, 2, PC, true, 3>(a, b, sM, q, live);
+  __syncthreads();
+  stage<T, PF, PF, PC, 1, PC, true, 3>(b, a, sM, q, live);
+  __syncthreads();
+  stage<T, PF, PC, PC, 0, PC, true, 3>(a, b, sM, q, live);
+  __syncthreads();
+  if (live && q < C3) {
+    const uint32_t w = emap_c[e * C3 + q];
+    const uint32_t node = w & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&rc[(int64_t)node * 3 + c], b[c * C3 + q]);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Strain energy per element (deterministic serial sum over the element's points).
+// ------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_energy(const uint32_t *__restrict__ emap,
+                                                      const double *__restrict__ u,
+                                                      const double *__restrict__ geo,
+                                                      const double *__restrict__ tab, double mu0,
+                                                      double lam0, const double *__restrict__ mu_e,
+                                                      const double *__restrict__ lam_e,
+                                                      double *__restrict__ out, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 3 * Q3, S1 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  if (live && q < P3) {
+    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a[c * P3 + q] = u[(int64_t)node * 3 + c];
+  }
+  __syncthreads();
+  interp<T, P, Q, 3>(a, b, sB, q, live);
+  T psi = 0;
+  if (live) {
+    T G[3][3], D[3][3];
+    grad_q<T, Q, 3>(b, sD, q, G);
+    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+    const T W = g[0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+    const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
+    Kin<T> k;
+    kinematics(G, D, mu, lam, k);
+    T tre = 0;
+    for (int i = 0; i < 3; ++i) {
+      tre += k.H[i][i];
+      for (int j = 0; j < 3; ++j) tre += 0.5 * k.H[i][j] * k.H[i][j];
+    }
+    psi = W * (0.5 * lam * k.logJ * k.logJ - mu * k.logJ + mu * tre);
+  }
+  __syncthreads();
+  if (live) a[q] = psi;
+  __syncthreads();
+  if (live && q == 0) {
+    T s = 0;
+    for (int i = 0; i < Q3; ++i) s += a[i];
+    out[e] = s;
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// a16: adjoint (vector-Jacobian product) of the masked residual.
+// ------------------------------------------------------------------------------------
+template <int P, int Q, bool STORED>
+__global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
+    const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ w,
+    const double *__restrict__ geo, const double *__restrict__ state, const double *__restrict__ tab,
+    double mu0, double lam0, const double *__restrict__ mu_e, const double *__restrict__ lam_e,
+    double *__restrict__ ub, double *__restrict__ mub, double *__restrict__ lamb, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int NC = STORED ? 3 : 6;
+  constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
+  if (live && q < P3) {
+    const uint32_t wd = emap[e * P3 + q];
+    const uint32_t node = wd & EMAP_ID_MASK;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      a[c * P3 + q] = ((wd >> (EMAP_BC_SHIFT + c)) & 1u) ? 0.0 : w[(int64_t)node * 3 + c];
+      if (!STORED) a[(3 + c) * P3 + q] = u[(int64_t)node * 3 + c];
+    }
+  }
+  __syncthreads();
+  interp<T, P, Q, NC>(a, b, sB, q, live);
+  T pm = 0, pl = 0;
+  if (live) {
+    T G[NC][3], C[3][3], A[3][3], tau[6], c, W;
+    grad_q<T, Q, NC>(b, sD, q, G);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) C[i][k] = G[i][k];
+    const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
+    T twoe[6];
+    double logJ;
+    if (STORED) {
+      const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[k][j] = s[(k * 3 + j) * NQ];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
+      c = s[15 * NQ];
+      W = s[16 * NQ];
+      // tau = 2 mu e + c I and c = lambda log J
+#pragma unroll
+      for (int m = 0; m < 6; ++m) twoe[m] = (tau[m] - (m < 3 ? c : 0.0)) / mu;
+      logJ = c / lam;
+    } else {
+      T Gu[3][3], D[3][3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Gu[i][k] = G[NC - 3 + i][k];
+      const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+      W = g[0];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+      Kin<T> k;
+      kinematics(Gu, D, mu, lam, k);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[i][j] = k.A[i][j];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) tau[m] = k.tau[m];
+      c = k.c;
+      logJ = k.logJ;
+      for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j)
+          twoe[sym_index(i, j)] = k.H[i][j] + k.H[j][i] +
+                                  k.H[i][0] * k.H[j][0] + k.H[i][1] * k.H[j][1] + k.H[i][2] * k.H[j][2];
+    }
+    T f[3][3], M[3][3];
+    adjoint_qf(C, A, tau, c, W, mu, lam, f, M);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) a[(i * 3 + k) * Q3 + q] = f[i][k];
+    T d = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) d += M[i][j] * twoe[sym_index(i, j)];
+    pm = W * d;
+    pl = W * logJ * (M[0][0] + M[1][1] + M[2][2]);
+  }
+  __syncthreads();
+  // per-element parameter gradients: stage the point values in b, sum serially
+  if (live) {
+    b[q] = pm;
+    b[Q3 + q] = pl;
+  }
+  grad_t_q<T, Q>(a, sD, q, b + 2 * Q3, live);
+  __syncthreads();
+  if (live && q == 0) {
+    T sm = 0, sl = 0;
+    for (int i = 0; i < Q3; ++i) {
+      sm += b[i];
+      sl += b[Q3 + i];
+    }
+    if (mub) mub[e] = sm;
+    if (lamb) lamb[e] = sl;
+  }
+  // move the transposed-gradient result to the front of b for interp_t
+  T tmp[3];
+  if (live) {
+#pragma unroll
+    for (int c2 = 0; c2 < 3; ++c2) tmp[c2] = b[2 * Q3 + c2 * Q3 + q];
+  }
+  __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int c2 = 0; c2 < 3; ++c2) b[c2 * Q3 + q] = tmp[c2];
+  }
+  __syncthreads();
+  interp_t<T, P, Q, 3>(b, a, sB, q, live);
+  if (live && q < P3) {
+    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
+#pragma unroll
+    for (int c2 = 0; c2 < 3; ++c2) atomic_add(&ub[(int64_t)node * 3 + c2], a[c2 * P3 + q]);
+  }
+}
+
+// Geometric factors out of the tiled layout into [E][10][Q^3].
+template <int Q>
+__global__ void k_export_geo(const double *__restrict__ geo, double *__restrict__ out, int64_t E) {
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = E * NGEO * Q3;
+  if (i >= total) return;
+  const int64_t e = i / (NGEO * Q3);
+  const int f = (int)((i / Q3) % NGEO), q = (int)(i % Q3);
+  const int64_t tile = e / ET;
+  const int el = (int)(e % ET);
+  out[i] = geo[(tile * NGEO + f) * NQ + el * Q3 + q];
+}
+
+// Internal element map with Dirichlet bits.
+__global__ void k_build_emap(const int32_t *__restrict__ en, const uint8_t *__restrict__ mask,
+                             uint32_t *__restrict__ emap, int64_t n, int64_t N,
+                             unsigned *__restrict__ flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t node = en[i];
+  if (node < 0 || node >= N) {
+    atomicOr(flags, 4u);
+    emap[i] = 0;
+    return;
+  }
+  uint32_t w = (uint32_t)node;
+  if (mask) {
+    for (int c = 0; c < 3; ++c)
+      if (mask[(int64_t)node * 3 + c]) w |= 1u << (EMAP_BC_SHIFT + c);
+  }
+  emap[i] = w;
+}
+
+__global__ void k_count(const uint32_t *__restrict__ emap, double *__restrict__ cnt, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) atomic_add(&cnt[emap[i] & EMAP_ID_MASK], 1.0);
+}
+
+__global__ void k_invert_count(double *__restrict__ c64, float *__restrict__ c32, int64_t N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double v = c64[i] > 0.0 ? 1.0 / c64[i] : 0.0;
+  c64[i] = v;
+  c32[i] = (float)v;
+}
+
+__global__ void k_zero_d(double *__restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+// ------------------------------------------------------------------------------------
+// (P, Q) dispatch.
+// ------------------------------------------------------------------------------------
+#define HPMG_PQ_LIST(X) \
+  X(2, 2) X(2, 3) X(2, 4) X(2, 5) X(3, 3) X(3, 4) X(3, 5) X(4, 4) X(4, 5) X(5, 5) X(5, 6)
+
+#define HPMG_PP_LIST(X) X(3, 2) X(4, 2) X(5, 2) X(4, 3) X(5, 3) X(5, 4)
+
+}  // namespace
+
+bool supported_pq(int P, int Q) {
+#define X(p, q) if (P == p && Q == q) return true;
+  HPMG_PQ_LIST(X)
+#undef X
+  return false;
+}
+
+static bool supported_pp(int Pf, int Pc) {
+#define X(f, c) if (Pf == f && Pc == c) return true;
+  HPMG_PP_LIST(X)
+#undef X
+  return false;
+}
+
+hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s) {
+  const int64_t n = op.E * op.P * op.P * op.P;
+  k_build_emap<<<grid1d(n, 256), 256, 0, s>>>(op.elem_nodes, op.mask, op.emap, n, op.N, op.flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_multiplicity(const hpmg_op_s &op, hipStream_t s) {
+  const int64_t n = op.E * op.P * op.P * op.P;
+  k_zero_d<<<grid1d(op.N, 256), 256, 0, s>>>(op.invmult64, op.N);
+  k_count<<<grid1d(n, 256), 256, 0, s>>>(op.emap, op.invmult64, n);
+  k_invert_count<<<grid1d(op.N, 256), 256, 0, s>>>(op.invmult64, op.invmult32, op.N);
+  return hipGetLastError();
+}
+
+hipError_t launch_qdata(const hpmg_op_s &op, const double *X, hipStream_t s) {
+#define X(p, q)                                                                              \
+  if (op.P == p && op.Q == q) {                                                              \
+    k_qdata<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, X, op.tab64, op.geo, op.flags, op.E); \
+    return hipGetLastError();                                                                \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
+  hipError_t e = launch_init_bc(HPMG_F64, op.N, op.mask, nullptr, r, s);
+  if (e != hipSuccess) return e;
+#define X(p, q)                                                                                  \
+  if (op.P == p && op.Q == q) {                                                                  \
+    k_residual<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, op.lam, \
+                                                              op.mu_e, op.lam_e, r,              \
+                                                              store ? op.state64 : nullptr, op.flags, op.E); \
+    return hipGetLastError();                                                                    \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,
+                           void *y, hipStream_t s) {
+  const hpmg_op_s &f = op.fine ? *op.fine : op;
+  hipError_t e = launch_init_bc(prec, op.N, op.mask, du, y, s);
+  if (e != hipSuccess) return e;
+  if (mode == HPMG_STORED) {
+    if (prec == HPMG_F64) {
+#define X(p, q)                                                                                     \
+  if (op.P == p && op.Q == q) {                                                                     \
+    k_jacobian_stored<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                        \
+        op.emap, (const double *)du, f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, (double *)y, op.E); \
+    return hipGetLastError();                                                                       \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    } else {
+#define X(p, q)                                                                                    \
+  if (op.P == p && op.Q == q) {                                                                    \
+    k_jacobian_stored<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                        \
+        op.emap, (const float *)du, f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e, (float *)y, op.E); \
+    return hipGetLastError();                                                                      \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    }
+  } else {
+    if (prec == HPMG_F64) {
+#define X(p, q)                                                                                      \
+  if (op.P == p && op.Q == q) {                                                                      \
+    k_jacobian_recompute<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                      \
+        op.emap, u, (const double *)du, op.geo, op.tab64, op.mu, op.lam, op.mu_e, op.lam_e, (double *)y, op.E); \
+    return hipGetLastError();                                                                        \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    } else {
+#define X(p, q)                                                                                     \
+  if (op.P == p && op.Q == q) {                                                                     \
+    k_jacobian_recompute<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                      \
+        op.emap, u, (const float *)du, op.geo, op.tab32, op.mu, op.lam, op.mu_e, op.lam_e, (float *)y, op.E); \
+    return hipGetLastError();                                                                       \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_diagonal(const hpmg_op_s &op, int prec, void *diag, hipStream_t s) {
+  const hpmg_op_s &f = op.fine ? *op.fine : op;
+  hipError_t e = launch_fill_bc_one(prec, op.N, op.mask, diag, s);
+  if (e != hipSuccess) return e;
+  if (prec == HPMG_F64) {
+#define X(p, q)                                                                                    \
+  if (op.P == p && op.Q == q) {                                                                    \
+    k_diagonal<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                              \
+        op.emap, f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, (double *)diag, op.E);     \
+    return hipGetLastError();                                                                      \
+  }
+    HPMG_PQ_LIST(X)
+#undef X
+  } else {
+#define X(p, q)                                                                                   \
+  if (op.P == p && op.Q == q) {                                                                   \
+    k_diagonal<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                              \
+        op.emap, f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e, (float *)diag, op.E);     \
+    return hipGetLastError();                                                                     \
+  }
+    HPMG_PQ_LIST(X)
+#undef X
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_prolong_add(const hpmg_op_s &c, const hpmg_op_s &f, int prec, const void *xc, void *yf,
+                              hipStream_t s) {
+  const unsigned grid = grid1d(f.E, elems_per_tile(f.P));
+#define X(pf, pc)                                                                                     \
+  if (f.P == pf && c.P == pc) {                                                                       \
+    if (prec == HPMG_F64)                                                                             \
+      k_prolong_add<double, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(c.emap, f.emap, (const double *)xc,    \
+                                                                f.invmult64, c.tab64, (double *)yf, f.E); \
+    else                                                                                              \
+      k_prolong_add<float, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(c.emap, f.emap, (const float *)xc,      \
+                                                               f.invmult32, c.tab32, (float *)yf, f.E); \
+    return hipGetLastError();                                                                         \
+  }
+  HPMG_PP_LIST(X)
+#undef X
+  (void)supported_pp;
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_restrict(const hpmg_op_s &f, const hpmg_op_s &c, int prec, const void *rf, void *rc,
+                           hipStream_t s) {
+  hipError_t e = launch_init_bc(prec, c.N, nullptr, nullptr, rc, s);
+  if (e != hipSuccess) return e;
+  const unsigned grid = grid1d(f.E, elems_per_tile(f.P));
+#define X(pf, pc)                                                                                    \
+  if (f.P == pf && c.P == pc) {                                                                      \
+    if (prec == HPMG_F64)                                                                            \
+      k_restrict<double, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, c.emap, (const double *)rf,      \
+                                                             f.invmult64, c.tab64, (double *)rc, f.E); \
+    else                                                                                             \
+      k_restrict<float, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, c.emap, (const float *)rf,        \
+                                                            f.invmult32, c.tab32, (float *)rc, f.E);  \
+    return hipGetLastError();                                                                        \
+  }
+  HPMG_PP_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipStream_t s) {
+#define X(p, q)                                                                                  \
+  if (op.P == p && op.Q == q) {                                                                  \
+    k_energy<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, op.lam, \
+                                                            op.mu_e, op.lam_e, op.scratch, op.E); \
+    hipError_t e = hipGetLastError();                                                            \
+    if (e != hipSuccess) return e;                                                               \
+    return launch_sum(op.E, op.scratch, op.scratch + op.E, psi, s);                              \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
+                      double *mub, double *lamb, hipStream_t s) {
+  hipError_t e = launch_init_bc(HPMG_F64, op.N, nullptr, nullptr, ub, s);
+  if (e != hipSuccess) return e;
+#define X(p, q)                                                                                      \
+  if (op.P == p && op.Q == q) {                                                                      \
+    if (mode == HPMG_STORED)                                                                         \
+      k_vjp<p, q, true><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,   \
+                                                                 op.tab64, op.mu, op.lam, op.mu_e,   \
+                                                                 op.lam_e, ub, mub, lamb, op.E);     \
+    else                                                                                             \
+      k_vjp<p, q, false><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,  \
+                                                                  op.tab64, op.mu, op.lam, op.mu_e,  \
+                                                                  op.lam_e, ub, mub, lamb, op.E);    \
+    return hipGetLastError();                                                                        \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s) {
+  const int64_t total = op.E * NGEO * op.Q * op.Q * op.Q;
+  switch (op.Q) {
+    case 2: k_export_geo<2><<<grid1d(total, 256), 256, 0, s>>>(op.geo, out, op.E); break;
+    case 3: k_export_geo<3><<<grid1d(total, 256), 256, 0, s>>>(op.geo, out, op.E); break;
+    case 4: k_export_geo<4><<<grid1d(total, 256), 256, 0, s>>>(op.geo, out, op.E); break;
+    case 5: k_export_geo<5><<<grid1d(total, 256), 256, 0, s>>>(op.geo, out, op.E); break;
+    case 6: k_export_geo<6><<<grid1d(total, 256), 256, 0, s>>>(op.geo, out, op.E); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hpmg

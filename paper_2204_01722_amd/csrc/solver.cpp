@@ -1,0 +1,505 @@
+// p-multigrid preconditioner, flexible CG and the Newton load-stepping driver
+// (Sections III-A and III-B).  Host orchestration only: every vector operation runs
+// in the library's kernels; the host reads back the few scalars that decide control
+// flow (CG coefficients, norms) through a pinned buffer.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace hpmg;
+
+namespace {
+
+inline size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+inline hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+struct Level {
+  hpmg_op_s *op = nullptr;
+  int64_t n = 0;  // scalars (3 * nodes)
+  void *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *z = nullptr, *dinv = nullptr;
+  double lam = 0.0;
+};
+
+}  // namespace
+
+struct hpmg_mg_s {
+  std::vector<Level> lv;
+  hpmg_mg_params prm{};
+  char *ws = nullptr;
+  size_t bytes = 0;
+  double *red = nullptr;     // reduction partials
+  double *scal = nullptr;    // device scalars (8)
+  double *host = nullptr;    // pinned host mirror (8)
+  // fine FP64 vectors for the Krylov and Newton drivers
+  double *fr = nullptr, *fr2 = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr;
+  double *nF = nullptr, *ndu = nullptr, *nut = nullptr;
+  int last_coarse_its = 0;
+  int setup_done = 0;
+};
+
+namespace {
+
+int prec_of(const hpmg_mg_s *mg) { return mg->prm.precision; }
+
+size_t mg_layout(hpmg_mg_s *mg, char *base) {
+  size_t o = 0;
+  const int prec = prec_of(mg);
+  const size_t es = prec_size(prec);
+  auto take = [&](size_t bytes) -> char * {
+    char *p = base ? base + o : nullptr;
+    o += align256(bytes);
+    return p;
+  };
+  mg->red = reinterpret_cast<double *>(take(2 * RED_BLOCKS * sizeof(double) * 2));
+  mg->scal = reinterpret_cast<double *>(take(16 * sizeof(double)));
+  for (Level &L : mg->lv) {
+    const size_t nb = (size_t)L.n * es;
+    L.b = take(nb);
+    L.x = take(nb);
+    L.r = take(nb);
+    L.d = take(nb);
+    L.t = take(nb);
+    L.z = take(nb);
+    L.dinv = take(nb);
+  }
+  const size_t nf = (size_t)mg->lv[0].n * sizeof(double);
+  mg->fr = reinterpret_cast<double *>(take(nf));
+  mg->fr2 = reinterpret_cast<double *>(take(nf));
+  mg->fz = reinterpret_cast<double *>(take(nf));
+  mg->fp = reinterpret_cast<double *>(take(nf));
+  mg->fq = reinterpret_cast<double *>(take(nf));
+  mg->nF = reinterpret_cast<double *>(take(nf));
+  mg->ndu = reinterpret_cast<double *>(take(nf));
+  mg->nut = reinterpret_cast<double *>(take(nf));
+  return o;
+}
+
+// Reads `count` device scalars from mg->scal (synchronises the stream).
+int read_scalars(hpmg_mg_s *mg, int count, hipStream_t s) {
+  HPMG_HIP(hipMemcpyAsync(mg->host, mg->scal, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  HPMG_HIP(hipStreamSynchronize(s));
+  return HPMG_OK;
+}
+
+int apply(const Level &L, int prec, const void *in, void *out, hipStream_t s) {
+  HPMG_HIP(launch_jacobian(*L.op, prec, HPMG_STORED, nullptr, in, out, s));
+  return HPMG_OK;
+}
+
+// Largest eigenvalue of a symmetric tridiagonal matrix by Sturm-sequence bisection.
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+  const int k = (int)a.size();
+  if (k == 0) return 0.0;
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < k; ++i) {
+    double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < k; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= k)
+      hi = mid;
+    else
+      lo = mid;
+    if (hi - lo <= 1e-15 * std::max(1.0, std::fabs(hi))) break;
+  }
+  return hi;
+}
+
+// Jacobi-PCG on level L from x = 0 with right-hand side L.b.  fixed > 0 runs exactly
+// that many iterations; otherwise stops at ||r|| <= rtol ||b||.  Records the CG
+// coefficients when asked (eigenvalue estimate).
+int pcg(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, hipStream_t s, int *its_out,
+        std::vector<double> *alphas, std::vector<double> *betas) {
+  int st;
+  HPMG_HIP(launch_init_bc(prec, L.n / 3, nullptr, nullptr, L.x, s));
+  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, 0.0, L.b, L.r, s));
+  HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, mg->scal, s));
+  if ((st = read_scalars(mg, 2, s))) return st;
+  double rz = mg->host[0];
+  const double bn = std::sqrt(mg->host[1]);
+  *its_out = 0;
+  if (fixed <= 0 && bn == 0.0) return HPMG_OK;
+  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.z, 0.0, L.z, L.d, s));
+  const int limit = fixed > 0 ? fixed : maxit;
+  int its = 0;
+  while (its < limit) {
+    if ((st = apply(L, prec, L.d, L.t, s))) return st;
+    HPMG_HIP(launch_dot(prec, L.n, L.d, L.t, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 1, s))) return st;
+    const double pq = mg->host[0];
+    if (!(pq > 0.0)) break;
+    const double alpha = rz / pq;
+    HPMG_HIP(launch_cg_update(prec, L.n, alpha, L.d, L.t, L.x, L.r, L.r, s));
+    ++its;
+    if (alphas) alphas->push_back(alpha);
+    HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 2, s))) return st;
+    const double rz_new = mg->host[0];
+    if (fixed <= 0 && std::sqrt(mg->host[1]) <= rtol * bn) break;
+    const double beta = rz_new / rz;
+    if (betas) betas->push_back(beta);
+    HPMG_HIP(launch_axpby(prec, L.n, 1.0, L.z, beta, L.d, s));
+    rz = rz_new;
+  }
+  *its_out = its;
+  return HPMG_OK;
+}
+
+// Chebyshev semi-iteration for D^{-1}A on [lo, hi] * lambda_max, `degree` updates of
+// L.x (Ax of the initial guess skipped when it is zero).
+int chebyshev(hpmg_mg_s *mg, Level &L, int prec, bool x_zero, hipStream_t s) {
+  int st;
+  const double a = mg->prm.cheb_lo * L.lam, bb = mg->prm.cheb_hi * L.lam;
+  const double theta = 0.5 * (bb + a), delta = 0.5 * (bb - a);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (x_zero) {
+    HPMG_HIP(launch_cheb_first(prec, L.n, L.dinv, L.b, nullptr, L.r, L.d, L.x, 1.0 / theta, s));
+  } else {
+    if ((st = apply(L, prec, L.x, L.t, s))) return st;
+    HPMG_HIP(launch_cheb_first(prec, L.n, L.dinv, L.b, L.t, L.r, L.d, L.x, 1.0 / theta, s));
+  }
+  for (int k = 1; k < mg->prm.cheb_degree; ++k) {
+    if ((st = apply(L, prec, L.d, L.t, s))) return st;
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    HPMG_HIP(launch_cheb_step(prec, L.n, L.dinv, L.r, L.t, L.d, L.x, rho_new * rho, 2.0 * rho_new / delta, s));
+    rho = rho_new;
+  }
+  return HPMG_OK;
+}
+
+int cycle(hpmg_mg_s *mg, int l, hipStream_t s) {
+  int st;
+  const int prec = prec_of(mg);
+  Level &L = mg->lv[l];
+  if (l + 1 == (int)mg->lv.size()) {
+    int its = 0;
+    st = pcg(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its, s, &its, nullptr,
+             nullptr);
+    mg->last_coarse_its = its;
+    return st;
+  }
+  Level &C = mg->lv[l + 1];
+  if ((st = chebyshev(mg, L, prec, true, s))) return st;
+  if ((st = apply(L, prec, L.x, L.t, s))) return st;
+  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, -1.0, L.t, L.r, s));
+  HPMG_HIP(launch_restrict(*L.op, *C.op, prec, L.r, C.b, s));
+  if ((st = cycle(mg, l + 1, s))) return st;
+  HPMG_HIP(launch_prolong_add(*C.op, *L.op, prec, C.x, L.x, s));
+  return chebyshev(mg, L, prec, false, s);
+}
+
+int vcycle(hpmg_mg_s *mg, const double *r, double *z, hipStream_t s) {
+  int st;
+  Level &L = mg->lv[0];
+  const int prec = prec_of(mg);
+  if (prec == HPMG_F64)
+    HPMG_HIP(launch_waxpby(HPMG_F64, L.n, 1.0, r, 0.0, r, L.b, s));
+  else
+    HPMG_HIP(launch_cast(L.n, HPMG_F32, r, L.b, s));
+  if ((st = cycle(mg, 0, s))) return st;
+  if (prec == HPMG_F64)
+    HPMG_HIP(launch_waxpby(HPMG_F64, L.n, 1.0, L.x, 0.0, L.x, z, s));
+  else
+    HPMG_HIP(launch_cast(L.n, HPMG_F64, L.x, z, s));
+  return HPMG_OK;
+}
+
+int mg_check(hpmg_mg_s *mg, const char *fn) {
+  if (!mg) return fail(HPMG_ERR_ARG, std::string(fn) + ": null multigrid handle");
+  if (!mg->ws) return fail(HPMG_ERR_WORKSPACE, std::string(fn) + ": workspace not bound");
+  return HPMG_OK;
+}
+
+int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
+  int st;
+  const int prec = prec_of(mg);
+  hpmg_op_s *fine = mg->lv[0].op;
+  if (!fine->state_ready) return fail(HPMG_ERR_ARG, "mg_setup: no stored linearisation on the fine operator");
+  if (prec == HPMG_F32) {
+    HPMG_HIP(launch_cast_state((int64_t)fine->tiles * fine->NQ * NSTATE, fine->state64, fine->state32, s));
+    fine->state32_ready = true;
+  }
+  for (Level &L : mg->lv) {
+    HPMG_HIP(launch_diagonal(*L.op, prec, L.dinv, s));
+    HPMG_HIP(launch_recip(prec, L.n, L.dinv, s));
+  }
+  for (size_t l = 0; l + 1 < mg->lv.size(); ++l) {
+    Level &L = mg->lv[l];
+    if (prec == HPMG_F64)
+      HPMG_HIP(launch_waxpby(HPMG_F64, L.n, 1.0, seeds[l], 0.0, seeds[l], L.b, s));
+    else
+      HPMG_HIP(launch_cast(L.n, HPMG_F32, seeds[l], L.b, s));
+    std::vector<double> al, be;
+    int its = 0;
+    if ((st = pcg(mg, L, prec, 0.0, 0, mg->prm.lanczos_its, s, &its, &al, &be))) return st;
+    if (al.empty()) return fail(HPMG_ERR_BREAKDOWN, "mg_setup: eigenvalue estimate broke down");
+    std::vector<double> diag(al.size()), off(al.size() > 1 ? al.size() - 1 : 0);
+    for (size_t j = 0; j < al.size(); ++j) {
+      diag[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+      if (j + 1 < al.size()) off[j] = std::sqrt(be[j]) / al[j];
+    }
+    L.lam = tridiag_max_eig(diag, off);
+    if (!(L.lam > 0.0) || !std::isfinite(L.lam)) return fail(HPMG_ERR_BREAKDOWN, "mg_setup: bad lambda_max");
+  }
+  mg->setup_done = 1;
+  return HPMG_OK;
+}
+
+int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol, int maxit, int *its_out,
+           double *rel_out, hipStream_t s) {
+  int st;
+  const int64_t n = mg->lv[0].n;
+  double *r = mg->fr, *rn = mg->fr2, *z = mg->fz, *p = mg->fp, *q = mg->fq;
+  *its_out = 0;
+  *rel_out = 0.0;
+  HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, x, q, s));
+  HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, b, -1.0, q, r, s));
+  HPMG_HIP(launch_dot(HPMG_F64, n, r, r, mg->red, mg->scal, s));
+  if ((st = read_scalars(mg, 1, s))) return st;
+  const double r0 = std::sqrt(mg->host[0]);
+  if (r0 == 0.0) return HPMG_OK;
+  if ((st = vcycle(mg, r, z, s))) return st;
+  HPMG_HIP(launch_dot(HPMG_F64, n, r, z, mg->red, mg->scal, s));
+  if ((st = read_scalars(mg, 1, s))) return st;
+  double rz = mg->host[0];
+  HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, z, 0.0, z, p, s));
+  int its = 0;
+  double rel = 1.0;
+  while (its < maxit) {
+    HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, p, q, s));
+    HPMG_HIP(launch_dot(HPMG_F64, n, p, q, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 1, s))) return st;
+    const double pq = mg->host[0];
+    if (!(pq > 0.0) || !std::isfinite(rz)) {
+      *its_out = its;
+      *rel_out = rel;
+      return fail(HPMG_ERR_BREAKDOWN, "fcg: p^T A p <= 0");
+    }
+    const double alpha = rz / pq;
+    HPMG_HIP(launch_cg_update(HPMG_F64, n, alpha, p, q, x, r, rn, s));
+    ++its;
+    HPMG_HIP(launch_dot(HPMG_F64, n, rn, rn, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 1, s))) return st;
+    rel = std::sqrt(mg->host[0]) / r0;
+    if (rel <= rtol) break;
+    if ((st = vcycle(mg, rn, z, s))) return st;
+    HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 2, s))) return st;
+    const double beta = (mg->host[0] - mg->host[1]) / rz;
+    rz = mg->host[0];
+    HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0, z, beta, p, s));
+    std::swap(r, rn);
+  }
+  *its_out = its;
+  *rel_out = rel;
+  if (rel > rtol) return fail(HPMG_ERR_NOT_CONVERGED, "fcg: iteration limit reached");
+  return HPMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void hpmg_mg_default_params(hpmg_mg_params *p) {
+  if (!p) return;
+  p->cheb_degree = 3;
+  p->cheb_lo = 0.1;
+  p->cheb_hi = 1.1;
+  p->lanczos_its = 10;
+  p->coarse_rtol = 1e-3;
+  p->coarse_maxit = 10000;
+  p->coarse_fixed_its = 0;
+  p->precision = HPMG_F64;
+}
+
+int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *params, hpmg_mg *out) {
+  if (!out || !levels || !params) return fail(HPMG_ERR_ARG, "mg_create: null argument");
+  *out = nullptr;
+  if (n_levels < 2) return fail(HPMG_ERR_ARG, "mg_create: need at least two levels");
+  if (params->precision != HPMG_F64 && params->precision != HPMG_F32)
+    return fail(HPMG_ERR_ARG, "mg_create: bad precision");
+  if (params->cheb_degree < 1 || !(params->cheb_lo > 0.0) || !(params->cheb_hi > params->cheb_lo) ||
+      params->lanczos_its < 1 || params->coarse_maxit < 1)
+    return fail(HPMG_ERR_ARG, "mg_create: bad smoother or coarse-solver parameters");
+  const hpmg_op_s *f = levels[0];
+  if (!f || f->fine) return fail(HPMG_ERR_ARG, "mg_create: levels[0] must be a fine operator");
+  for (int l = 1; l < n_levels; ++l) {
+    if (!levels[l] || levels[l]->fine != f)
+      return fail(HPMG_ERR_ARG, "mg_create: coarse levels must be coarse operators of levels[0]");
+    if (levels[l]->P >= levels[l - 1]->P) return fail(HPMG_ERR_ARG, "mg_create: orders must decrease");
+  }
+  hpmg_mg_s *mg = new hpmg_mg_s();
+  mg->prm = *params;
+  for (int l = 0; l < n_levels; ++l) {
+    Level L;
+    L.op = levels[l];
+    L.n = 3 * levels[l]->N;
+    mg->lv.push_back(L);
+  }
+  if (hipHostMalloc((void **)&mg->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    delete mg;
+    return fail(HPMG_ERR_HIP, "mg_create: pinned host buffer");
+  }
+  *out = mg;
+  return HPMG_OK;
+}
+
+void hpmg_mg_destroy(hpmg_mg mg) {
+  if (!mg) return;
+  if (mg->host) (void)hipHostFree(mg->host);
+  delete mg;
+}
+
+int hpmg_mg_workspace_bytes(hpmg_mg mg, size_t *bytes) {
+  if (!mg || !bytes) return fail(HPMG_ERR_ARG, "mg_workspace_bytes: null argument");
+  *bytes = mg_layout(mg, nullptr);
+  return HPMG_OK;
+}
+
+int hpmg_mg_bind_workspace(hpmg_mg mg, void *ws, size_t bytes) {
+  if (!mg || !ws) return fail(HPMG_ERR_ARG, "mg_bind_workspace: null argument");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(HPMG_ERR_ARG, "mg_bind_workspace: not 256-byte aligned");
+  if (bytes < mg_layout(mg, nullptr)) return fail(HPMG_ERR_WORKSPACE, "mg_bind_workspace: buffer too small");
+  mg->ws = static_cast<char *>(ws);
+  mg->bytes = bytes;
+  mg_layout(mg, mg->ws);
+  mg->setup_done = 0;
+  return HPMG_OK;
+}
+
+int hpmg_mg_setup(hpmg_mg mg, const double *const *seeds, void *stream) {
+  int st = mg_check(mg, "mg_setup");
+  if (st) return st;
+  if (!seeds) return fail(HPMG_ERR_ARG, "mg_setup: null seeds");
+  for (size_t l = 0; l + 1 < mg->lv.size(); ++l)
+    if (!seeds[l]) return fail(HPMG_ERR_ARG, "mg_setup: null seed vector");
+  for (const Level &L : mg->lv)
+    if (!L.op->ws) return fail(HPMG_ERR_WORKSPACE, "mg_setup: level operator without workspace");
+  return do_setup(mg, seeds, S(stream));
+}
+
+int hpmg_mg_vcycle(hpmg_mg mg, const double *r, double *z, void *stream) {
+  int st = mg_check(mg, "mg_vcycle");
+  if (st) return st;
+  if (!mg->setup_done) return fail(HPMG_ERR_ARG, "mg_vcycle: call mg_setup first");
+  if (!r || !z) return fail(HPMG_ERR_ARG, "mg_vcycle: null vector");
+  return vcycle(mg, r, z, S(stream));
+}
+
+int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its) {
+  if (!mg) return fail(HPMG_ERR_ARG, "mg_info: null handle");
+  if (level < 0 || level >= (int)mg->lv.size()) return fail(HPMG_ERR_ARG, "mg_info: bad level");
+  if (lambda_max) *lambda_max = mg->lv[level].lam;
+  if (last_coarse_its) *last_coarse_its = mg->last_coarse_its;
+  return HPMG_OK;
+}
+
+int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double rtol, int maxit, int *its,
+                   double *relres, void *stream) {
+  int st = mg_check(mg, "fcg_solve");
+  if (st) return st;
+  if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "fcg_solve: operator is not the mg fine level");
+  if (!b || !x || !its || !relres) return fail(HPMG_ERR_ARG, "fcg_solve: null argument");
+  if (!mg->setup_done) return fail(HPMG_ERR_ARG, "fcg_solve: call mg_setup first");
+  if (!(rtol > 0.0) || maxit < 1) return fail(HPMG_ERR_ARG, "fcg_solve: bad tolerance");
+  return do_fcg(fine, mg, b, x, rtol, maxit, its, relres, S(stream));
+}
+
+void hpmg_newton_default_params(hpmg_newton_params *p) {
+  if (!p) return;
+  p->rtol = 1e-8;
+  p->max_newton = 20;
+  p->lin_rtol = 1e-3;
+  p->lin_maxit = 500;
+  p->line_search = 1;
+}
+
+int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+                      const hpmg_newton_params *prm, const double *const *seeds, double *stats, void *stream) {
+  int st = mg_check(mg, "newton_solve");
+  if (st) return st;
+  if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "newton_solve: operator is not the mg fine level");
+  if (!u || !lift || !prm || !seeds || !stats) return fail(HPMG_ERR_ARG, "newton_solve: null argument");
+  if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "newton_solve: 1 <= n_steps <= 60");
+  if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "newton_solve: call qdata_setup first");
+  hipStream_t s = S(stream);
+  const int64_t n = mg->lv[0].n;
+  double *F = mg->nF, *du = mg->ndu, *ut = mg->nut;
+  for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;
+  int total_newton = 0, total_lin = 0, failed = 0;
+  double final_rel = 0.0;
+  for (int step = 0; step < n_steps; ++step) {
+    HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0 / n_steps, lift, 1.0, u, s));
+    HPMG_HIP(launch_residual(*fine, u, F, true, s));
+    fine->state_ready = true;
+    fine->state32_ready = false;
+    HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 1, s))) return st;
+    const double f0 = std::sqrt(mg->host[0]);
+    double fn = f0;
+    int its = 0;
+    while (its < prm->max_newton && fn > prm->rtol * f0 && f0 > 0.0) {
+      unsigned fl = 0;
+      if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
+      if (fl & HPMG_FLAG_NONPOSITIVE_J) return fail(HPMG_ERR_NONPOSITIVE_J, "newton_solve: inverted element");
+      if (fl & HPMG_FLAG_NONFINITE) return fail(HPMG_ERR_NONFINITE, "newton_solve: non-finite residual");
+      if ((st = do_setup(mg, seeds, s))) return st;
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, F, 0.0, F, ut, s));
+      HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
+      int lits = 0;
+      double lrel = 0.0;
+      st = do_fcg(fine, mg, ut, du, prm->lin_rtol, prm->lin_maxit, &lits, &lrel, s);
+      total_lin += lits;
+      if (st && st != HPMG_ERR_NOT_CONVERGED) return st;
+      double alpha = 1.0;
+      if (prm->line_search) {
+        // g(a) = F(u + a du)^T du; one secant step from a = 0 and a = 1.
+        HPMG_HIP(launch_dot(HPMG_F64, n, F, du, mg->red, mg->scal, s));
+        if ((st = read_scalars(mg, 1, s))) return st;
+        const double g0 = mg->host[0];
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 1.0, du, ut, s));
+        HPMG_HIP(launch_residual(*fine, ut, mg->fq, false, s));
+        HPMG_HIP(launch_dot(HPMG_F64, n, mg->fq, du, mg->red, mg->scal, s));
+        if ((st = read_scalars(mg, 1, s))) return st;
+        const double g1 = mg->host[0];
+        if (g0 - g1 > 0.0) alpha = std::min(1.5, std::max(0.1, g0 / (g0 - g1)));
+      }
+      HPMG_HIP(launch_axpby(HPMG_F64, n, alpha, du, 1.0, u, s));
+      HPMG_HIP(launch_residual(*fine, u, F, true, s));
+      fine->state32_ready = false;
+      HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
+      if ((st = read_scalars(mg, 1, s))) return st;
+      fn = std::sqrt(mg->host[0]);
+      ++its;
+    }
+    final_rel = f0 > 0.0 ? fn / f0 : 0.0;
+    if (fn > prm->rtol * f0) ++failed;
+    total_newton += its;
+    stats[4 + step] = its;
+  }
+  stats[0] = total_newton;
+  stats[1] = total_lin;
+  stats[2] = final_rel;
+  stats[3] = failed;
+  if (failed) return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: a load step did not converge");
+  return HPMG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,342 @@
+// Vector kernels for the Krylov and multigrid drivers: boundary-condition fills,
+// precision casts, fused axpy-type updates, and deterministic FP64 reductions.
+//
+// Reductions run on a fixed grid (RED_BLOCKS workgroups of 256 threads): each thread
+// accumulates a grid-strided slice in double, a 64-lane wavefront reduces with
+// cross-lane shuffles, the four wavefronts of a workgroup combine through LDS, and a
+// single workgroup sums the RED_BLOCKS partials in a fixed tree.  The result does not
+// depend on timing, so repeated runs are bitwise identical.
+#include "common.h"
+
+namespace hpmg {
+namespace {
+
+constexpr int BS = 256;
+
+inline unsigned grid_for(int64_t n) {
+  int64_t g = (n + BS - 1) / BS;
+  if (g < 1) g = 1;
+  if (g > 65535 * 16) g = 65535 * 16;
+  return (unsigned)g;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+template <typename T>
+__global__ void k_init_bc(int64_t nn, const uint8_t *__restrict__ mask, const T *__restrict__ x,
+                          T *__restrict__ y) {
+  GRID_STRIDE(i, 3 * nn) { y[i] = (mask && x && mask[i]) ? x[i] : T(0); }
+}
+
+template <typename T>
+__global__ void k_fill_bc_one(int64_t nn, const uint8_t *__restrict__ mask, T *__restrict__ y) {
+  GRID_STRIDE(i, 3 * nn) { y[i] = (mask && mask[i]) ? T(1) : T(0); }
+}
+
+__global__ void k_cast_d2f(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
+  GRID_STRIDE(i, n) { b[i] = (float)a[i]; }
+}
+
+__global__ void k_cast_f2d(int64_t n, const float *__restrict__ a, double *__restrict__ b) {
+  GRID_STRIDE(i, n) { b[i] = (double)a[i]; }
+}
+
+template <typename T>
+__global__ void k_axpby(int64_t n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
+  GRID_STRIDE(i, n) { y[i] = a * x[i] + b * y[i]; }
+}
+
+template <typename T>
+__global__ void k_waxpby(int64_t n, T a, const T *__restrict__ x, T b, const T *__restrict__ y,
+                         T *__restrict__ w) {
+  GRID_STRIDE(i, n) { w[i] = a * x[i] + b * y[i]; }
+}
+
+template <typename T>
+__global__ void k_cg_update(int64_t n, T alpha, const T *__restrict__ p, const T *__restrict__ q,
+                            T *__restrict__ x, const T *__restrict__ rin, T *__restrict__ rout) {
+  GRID_STRIDE(i, n) {
+    x[i] += alpha * p[i];
+    rout[i] = rin[i] - alpha * q[i];
+  }
+}
+
+template <typename T>
+__global__ void k_mul(int64_t n, const T *__restrict__ a, const T *__restrict__ x, T *__restrict__ y) {
+  GRID_STRIDE(i, n) { y[i] = a[i] * x[i]; }
+}
+
+template <typename T>
+__global__ void k_recip(int64_t n, T *__restrict__ x) {
+  GRID_STRIDE(i, n) { x[i] = T(1) / x[i]; }
+}
+
+// r = Dinv (b - Ax); d = r / theta; x = d (Ax == null: zero initial guess) or x += d.
+template <typename T>
+__global__ void k_cheb_first(int64_t n, const T *__restrict__ dinv, const T *__restrict__ b,
+                             const T *__restrict__ Ax, T *__restrict__ r, T *__restrict__ d,
+                             T *__restrict__ x, T inv_theta) {
+  GRID_STRIDE(i, n) {
+    const T ri = dinv[i] * (Ax ? b[i] - Ax[i] : b[i]);
+    const T di = ri * inv_theta;
+    r[i] = ri;
+    d[i] = di;
+    x[i] = Ax ? x[i] + di : di;
+  }
+}
+
+// r -= Dinv A d; d = c1 d + c2 r; x += d.
+template <typename T>
+__global__ void k_cheb_step(int64_t n, const T *__restrict__ dinv, T *__restrict__ r,
+                            const T *__restrict__ Ad, T *__restrict__ d, T *__restrict__ x, T c1, T c2) {
+  GRID_STRIDE(i, n) {
+    const T ri = r[i] - dinv[i] * Ad[i];
+    const T di = c1 * d[i] + c2 * ri;
+    r[i] = ri;
+    d[i] = di;
+    x[i] += di;
+  }
+}
+
+// ---- reductions -------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block sum of NV values per thread into out[v * gridDim.x + blockIdx.x].
+template <int NV>
+__device__ __forceinline__ void block_store(double (&v)[NV], double *__restrict__ partial) {
+  __shared__ double s[NV][BS / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const double w = wave_sum(v[k]);
+    if (lane == 0) s[k][wid] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double t = 0.0;
+      for (int j = 0; j < BS / 64; ++j) t += s[k][j];
+      partial[k * gridDim.x + blockIdx.x] = t;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dot_partial(int64_t n, const T *__restrict__ x,
+                                                    const T *__restrict__ y, double *__restrict__ partial) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) { v[0] += (double)x[i] * (double)y[i]; }
+  block_store<1>(v, partial);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dot2_partial(int64_t n, const T *__restrict__ x,
+                                                     const T *__restrict__ y, const T *__restrict__ z,
+                                                     double *__restrict__ partial) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    v[0] += (double)x[i] * (double)y[i];
+    v[1] += (double)z[i] * (double)z[i];
+  }
+  block_store<2>(v, partial);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_jacobi_dot_partial(int64_t n, const T *__restrict__ dinv,
+                                                           const T *__restrict__ r, T *__restrict__ z,
+                                                           double *__restrict__ partial) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const T ri = r[i];
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_store<2>(v, partial);
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_dot_pair_partial(int64_t n, const T *__restrict__ z,
+                                                         const T *__restrict__ a, const T *__restrict__ b,
+                                                         double *__restrict__ partial) {
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    const double zi = (double)z[i];
+    v[0] += zi * (double)a[i];
+    v[1] += zi * (double)b[i];
+  }
+  block_store<2>(v, partial);
+}
+
+__global__ __launch_bounds__(BS) void k_sum_partial(int64_t n, const double *__restrict__ x,
+                                                    double *__restrict__ partial) {
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) { v[0] += x[i]; }
+  block_store<1>(v, partial);
+}
+
+// One workgroup: out[k] = sum of partial[k * nb .. k * nb + nb) in a fixed tree.
+__global__ __launch_bounds__(RED_BLOCKS) void k_final(const double *__restrict__ partial, int nb, int nv,
+                                                      double *__restrict__ out) {
+  __shared__ double s[RED_BLOCKS];
+  for (int k = 0; k < nv; ++k) {
+    s[threadIdx.x] = threadIdx.x < (unsigned)nb ? partial[k * nb + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = RED_BLOCKS / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[k] = s[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t prec_size(int prec) { return prec == HPMG_F64 ? sizeof(double) : sizeof(float); }
+
+#define DISPATCH(prec, CALL_D, CALL_F) \
+  do {                                 \
+    if ((prec) == HPMG_F64) {          \
+      CALL_D;                          \
+    } else {                           \
+      CALL_F;                          \
+    }                                  \
+    return hipGetLastError();          \
+  } while (0)
+
+hipError_t launch_init_bc(int prec, int64_t nn, const uint8_t *mask, const void *x, void *y, hipStream_t s) {
+  DISPATCH(prec, (k_init_bc<double><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (const double *)x, (double *)y)),
+           (k_init_bc<float><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (const float *)x, (float *)y)));
+}
+
+hipError_t launch_fill_bc_one(int prec, int64_t nn, const uint8_t *mask, void *y, hipStream_t s) {
+  DISPATCH(prec, (k_fill_bc_one<double><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (double *)y)),
+           (k_fill_bc_one<float><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (float *)y)));
+}
+
+hipError_t launch_cast_state(int64_t n, const double *a, float *b, hipStream_t s) {
+  k_cast_d2f<<<grid_for(n), BS, 0, s>>>(n, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(int64_t n, int to_prec, const void *x, void *y, hipStream_t s) {
+  if (to_prec == HPMG_F32)
+    k_cast_d2f<<<grid_for(n), BS, 0, s>>>(n, (const double *)x, (float *)y);
+  else
+    k_cast_f2d<<<grid_for(n), BS, 0, s>>>(n, (const float *)x, (double *)y);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int prec, int64_t n, double a, const void *x, double b, void *y, hipStream_t s) {
+  DISPATCH(prec, (k_axpby<double><<<grid_for(n), BS, 0, s>>>(n, a, (const double *)x, b, (double *)y)),
+           (k_axpby<float><<<grid_for(n), BS, 0, s>>>(n, (float)a, (const float *)x, (float)b, (float *)y)));
+}
+
+hipError_t launch_waxpby(int prec, int64_t n, double a, const void *x, double b, const void *y, void *w,
+                         hipStream_t s) {
+  DISPATCH(prec,
+           (k_waxpby<double><<<grid_for(n), BS, 0, s>>>(n, a, (const double *)x, b, (const double *)y, (double *)w)),
+           (k_waxpby<float><<<grid_for(n), BS, 0, s>>>(n, (float)a, (const float *)x, (float)b, (const float *)y,
+                                                       (float *)w)));
+}
+
+hipError_t launch_cg_update(int prec, int64_t n, double alpha, const void *p, const void *q, void *x,
+                            const void *rin, void *rout, hipStream_t s) {
+  DISPATCH(prec,
+           (k_cg_update<double><<<grid_for(n), BS, 0, s>>>(n, alpha, (const double *)p, (const double *)q,
+                                                           (double *)x, (const double *)rin, (double *)rout)),
+           (k_cg_update<float><<<grid_for(n), BS, 0, s>>>(n, (float)alpha, (const float *)p, (const float *)q,
+                                                          (float *)x, (const float *)rin, (float *)rout)));
+}
+
+hipError_t launch_mul(int prec, int64_t n, const void *a, const void *x, void *y, hipStream_t s) {
+  DISPATCH(prec, (k_mul<double><<<grid_for(n), BS, 0, s>>>(n, (const double *)a, (const double *)x, (double *)y)),
+           (k_mul<float><<<grid_for(n), BS, 0, s>>>(n, (const float *)a, (const float *)x, (float *)y)));
+}
+
+hipError_t launch_recip(int prec, int64_t n, void *x, hipStream_t s) {
+  DISPATCH(prec, (k_recip<double><<<grid_for(n), BS, 0, s>>>(n, (double *)x)),
+           (k_recip<float><<<grid_for(n), BS, 0, s>>>(n, (float *)x)));
+}
+
+hipError_t launch_cheb_first(int prec, int64_t n, const void *dinv, const void *b, const void *Ax, void *r,
+                             void *d, void *x, double inv_theta, hipStream_t s) {
+  DISPATCH(prec,
+           (k_cheb_first<double><<<grid_for(n), BS, 0, s>>>(n, (const double *)dinv, (const double *)b,
+                                                            (const double *)Ax, (double *)r, (double *)d,
+                                                            (double *)x, inv_theta)),
+           (k_cheb_first<float><<<grid_for(n), BS, 0, s>>>(n, (const float *)dinv, (const float *)b,
+                                                           (const float *)Ax, (float *)r, (float *)d,
+                                                           (float *)x, (float)inv_theta)));
+}
+
+hipError_t launch_cheb_step(int prec, int64_t n, const void *dinv, void *r, const void *Ad, void *d, void *x,
+                            double c1, double c2, hipStream_t s) {
+  DISPATCH(prec,
+           (k_cheb_step<double><<<grid_for(n), BS, 0, s>>>(n, (const double *)dinv, (double *)r,
+                                                           (const double *)Ad, (double *)d, (double *)x, c1, c2)),
+           (k_cheb_step<float><<<grid_for(n), BS, 0, s>>>(n, (const float *)dinv, (float *)r, (const float *)Ad,
+                                                          (float *)d, (float *)x, (float)c1, (float)c2)));
+}
+
+hipError_t launch_dot(int prec, int64_t n, const void *x, const void *y, double *partial, double *out,
+                      hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_dot_partial<double><<<RED_BLOCKS, BS, 0, s>>>(n, (const double *)x, (const double *)y, partial);
+  else
+    k_dot_partial<float><<<RED_BLOCKS, BS, 0, s>>>(n, (const float *)x, (const float *)y, partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2(int prec, int64_t n, const void *x, const void *y, const void *z, double *partial,
+                       double *out, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_dot2_partial<double><<<RED_BLOCKS, BS, 0, s>>>(n, (const double *)x, (const double *)y, (const double *)z,
+                                                     partial);
+  else
+    k_dot2_partial<float><<<RED_BLOCKS, BS, 0, s>>>(n, (const float *)x, (const float *)y, (const float *)z,
+                                                    partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_jacobi_dot(int prec, int64_t n, const void *dinv, const void *r, void *z, double *partial,
+                             double *out, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_jacobi_dot_partial<double><<<RED_BLOCKS, BS, 0, s>>>(n, (const double *)dinv, (const double *)r,
+                                                           (double *)z, partial);
+  else
+    k_jacobi_dot_partial<float><<<RED_BLOCKS, BS, 0, s>>>(n, (const float *)dinv, (const float *)r, (float *)z,
+                                                          partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot_pair(int prec, int64_t n, const void *z, const void *a, const void *b, double *partial,
+                           double *out, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_dot_pair_partial<double><<<RED_BLOCKS, BS, 0, s>>>(n, (const double *)z, (const double *)a,
+                                                         (const double *)b, partial);
+  else
+    k_dot_pair_partial<float><<<RED_BLOCKS, BS, 0, s>>>(n, (const float *)z, (const float *)a, (const float *)b,
+                                                        partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 2, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(int64_t n, const double *x, double *partial, double *out, hipStream_t s) {
+  k_sum_partial<<<RED_BLOCKS, BS, 0, s>>>(n, x, partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 1, out);
+  return hipGetLastError();
+}
+
+}  // namespace hpmg

@@ -1,0 +1,90 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared symbol,
+tabulates the reference tables correctly, and rejects bad arguments on the host."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from _support import ROOT, ensure_built
+from oracle import basis as obasis
+
+
+@pytest.fixture(scope="module")
+def L():
+    ensure_built()
+    from paper_2204_01722_amd import binding
+    return binding.lib()
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hpmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpmg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) > 30
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2204_01722_amd import binding
+    assert set(binding.EXPORTED) == set(names)
+
+
+@pytest.mark.parametrize("P,Q", [(2, 2), (3, 3), (4, 4), (5, 5), (3, 5), (2, 5), (5, 6)])
+def test_tabulation_matches_oracle(L, P, Q):
+    from paper_2204_01722_amd.binding import hpmg_basis_tabulate
+    t = hpmg_basis_tabulate(P, Q)
+    o = obasis.tables_1d(P, Q)
+    np.testing.assert_allclose(t["interp"], o["B"], atol=2e-15)
+    np.testing.assert_allclose(t["grad"], o["D"], atol=5e-14)
+    np.testing.assert_allclose(t["qref"], o["xq"], atol=1e-15)
+    np.testing.assert_allclose(t["qweight"], o["wq"], atol=1e-15)
+    np.testing.assert_allclose(t["gll"], o["nodes"], atol=1e-15)
+    # collocated derivative reproduces the derivative table (full column rank, Q >= P)
+    np.testing.assert_allclose(t["colloc"] @ t["interp"], t["grad"], atol=5e-13)
+
+
+@pytest.mark.parametrize("Pf,Pc", [(3, 2), (5, 3), (5, 2), (4, 3), (5, 4)])
+def test_ctof_matches_oracle(L, Pf, Pc):
+    from paper_2204_01722_amd.binding import hpmg_basis_ctof
+    M = hpmg_basis_ctof(Pf, Pc)
+    nodes_c = obasis.gll_nodes(Pc)
+    ref, _ = obasis.lagrange(nodes_c, obasis.gll_nodes(Pf))
+    np.testing.assert_allclose(M, ref, atol=1e-14)
+
+
+def test_host_argument_validation(L):
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)  # never dereferenced by create/workspace queries
+    assert L.hpmg_basis_tabulate(1, 3, None, None, None, None, None, None) == 1
+    assert L.hpmg_basis_tabulate(4, 3, None, None, None, None, None, None) == 1
+    assert L.hpmg_op_create(3, 3, 10, 100, None, None, C.byref(h)) == 1
+    assert L.hpmg_op_create(6, 6, 10, 100, fake, None, C.byref(h)) == 3
+    assert L.hpmg_op_create(3, 3, 0, 100, fake, None, C.byref(h)) == 2
+    assert L.hpmg_op_create(3, 3, 10, 1 << 28, fake, None, C.byref(h)) == 2
+    assert L.hpmg_op_create(3, 3, 10, 100, fake, None, C.byref(h)) == 0
+    nb = C.c_size_t()
+    assert L.hpmg_op_workspace_bytes(h, C.byref(nb)) == 0
+    # workspace: tables + map + multiplicities + scratch + 10 + 17 + 17/2 doubles per point
+    assert nb.value > 10 * 27 * (10 + 17) * 8
+    assert L.hpmg_residual(h, fake, fake, 1, None) == 4  # workspace not bound
+    assert b"workspace" in L.hpmg_last_error()
+    assert L.hpmg_op_set_material(h, 1.0, 1.0, fake, None) == 1
+    hc = C.c_void_p()
+    assert L.hpmg_op_create_coarse(h, 3, 50, fake, None, C.byref(hc)) == 1  # not lower order
+    assert L.hpmg_op_create_coarse(h, 2, 50, fake, None, C.byref(hc)) == 0
+    assert L.hpmg_op_create_coarse(hc, 2, 50, fake, None, C.byref(C.c_void_p())) == 1
+    L.hpmg_op_destroy(hc)
+    L.hpmg_op_destroy(h)
+    assert L.hpmg_status_string(6) == b"non-positive Jacobian determinant"
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2204_01722_amd import binding
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(RuntimeError, match="no fallback"):
+        binding.lib()

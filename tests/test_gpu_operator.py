@@ -1,0 +1,242 @@
+"""GPU parity of the fused operator kernels against the FP64 oracle (same seeded inputs).
+
+FP64 results must match to 1e-12 relative (2-norm), FP32 applies to 1e-5."""
+import numpy as np
+import pytest
+
+from _support import LAM, MU, ensure_built, gpu_available, incident_elements, print_case, rel, t2n
+from oracle import basis as obasis
+from oracle import fem, mg as omg
+from paper_2204_01722_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    ensure_built()
+
+
+def _setup(n, p, jitter=0.05, faces=None, orders=None, q=None, mu_e=None, lam_e=None, L=(1.0, 1.0, 1.0)):
+    from paper_2204_01722_amd.problem import Hierarchy
+    m = inputs.box_mesh(n, p, L=L, jitter=jitter)
+    H = Hierarchy(m, orders or [p], faces=faces, q=q, mu_e=mu_e, lam_e=lam_e)
+    return m, H
+
+
+def _dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+@pytest.mark.parametrize("n,p,q", [(3, 1, 2), (3, 2, 3), (2, 3, 4), (2, 4, 5), (2, 2, 4), ((3, 2, 1), 2, 3)])
+def test_qdata(n, p, q):
+    print_case("qdata", n=n, p=p, q=q)
+    m, H = _setup(n, p, jitter=0.08, q=q)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P, q)
+    W, dxidX = fem.qdata(d)
+    g = t2n(H.fine.qdata_export())
+    assert rel(g[:, 0, :], W) < TOL64
+    assert rel(g[:, 1:, :].reshape(m.n_elem, 3, 3, -1).transpose(0, 3, 1, 2), dxidX) < TOL64
+    assert abs(g[:, 0, :].sum() - 1.0) < 1e-13
+    assert H.fine.query_flags() == 0
+
+
+CASES = [  # (n, p, q, faces)
+    (4, 2, 3, None),                                   # the 2,187-DoF parity case
+    (4, 2, 3, {"x0": (1, 1, 1), "x1": (1, 0, 0)}),
+    ((3, 2, 2), 1, 2, {"y0": (0, 1, 0)}),
+    ((2, 3, 2), 3, 4, {"z1": (1, 1, 1)}),
+    (2, 4, 5, {"x0": (1, 1, 1)}),
+    (3, 2, 4, None),                                   # Q = P + 1
+    ((3, 2, 1), 2, 3, None),                           # ragged last tile
+    (1, 2, 3, None),                                   # a single element
+]
+
+
+def _oracle_problem(m, q, faces, amplitude=0.05):
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P, q)
+    mask = inputs.face_mask(m, faces) if faces else None
+    u = inputs.config1_u(m, amplitude=amplitude)
+    du = inputs.random_vector(m.n_nodes, 2)
+    return d, mask, u, du
+
+
+@pytest.mark.parametrize("n,p,q,faces", CASES)
+def test_residual_and_jacobian(n, p, q, faces):
+    import torch
+    print_case("residual_jacobian", n=n, p=p, q=q, faces=faces)
+    m, H = _setup(n, p, faces=faces, q=q)
+    d, mask, u, du = _oracle_problem(m, q, faces)
+    op = H.fine
+    ut, dut = _dev(u), _dev(du)
+    r = op.residual(ut, store_state=True)
+    r_ref = fem.residual(d, u, MU, LAM, mask)
+    assert rel(t2n(r), r_ref) < TOL64
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
+    y = op.jacobian(dut, "f64", "stored")
+    assert rel(t2n(y), y_ref) < TOL64
+    y = op.jacobian(dut, "f64", "recompute", u=ut)
+    assert rel(t2n(y), y_ref) < TOL64
+    op.state_cast_f32()
+    y32 = op.jacobian(dut.float(), "f32", "stored")
+    assert y32.dtype == torch.float32
+    assert rel(t2n(y32), y_ref) < TOL32
+    y32 = op.jacobian(dut.float(), "f32", "recompute", u=ut)
+    assert rel(t2n(y32), y_ref) < TOL32
+    if mask is not None:
+        mb = mask.astype(bool)
+        assert np.all(t2n(y)[mb] == du[mb])
+        assert np.all(t2n(r)[mb] == 0.0)
+    assert op.query_flags() == 0
+
+
+@pytest.mark.parametrize("n,p,q,faces", CASES[:5])
+def test_diagonal(n, p, q, faces):
+    print_case("diagonal", n=n, p=p, q=q, faces=faces)
+    m, H = _setup(n, p, faces=faces, q=q)
+    d, mask, u, _ = _oracle_problem(m, q, faces)
+    op = H.fine
+    op.residual(_dev(u), store_state=True)
+    ref = fem.diagonal(d, u, MU, LAM, mask)
+    assert rel(t2n(op.diagonal("f64")), ref) < TOL64
+    op.state_cast_f32()
+    assert rel(t2n(op.diagonal("f32")), ref) < TOL32
+
+
+def _levels_oracle(m, H, u, faces):
+    """Oracle prolongations and Galerkin level operators for H's orders."""
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P, H.fine.Q)
+    K = fem.tangent_matrix(d, u, MU, LAM)
+    Ps, Ks = [], [K]
+    for l in range(1, len(H.orders)):
+        Pf, Pc = H.orders[l - 1] + 1, H.orders[l] + 1
+        Pm = omg.prolongation(H.topos[l - 1], Pf, H.ops[l - 1].n_nodes, H.topos[l], Pc, H.ops[l].n_nodes)
+        Ps.append(Pm)
+        Ks.append(omg.galerkin(Ks[-1], Pm))
+    return Ps, Ks
+
+
+@pytest.mark.parametrize("n,orders,faces", [
+    (2, [2, 1], {"x0": (1, 1, 1)}),
+    (2, [4, 2, 1], {"x0": (1, 1, 1), "x1": (1, 0, 0)}),
+    ((2, 3, 1), [3, 1], None),
+    (2, [4, 3], {"y1": (0, 1, 1)}),
+])
+def test_coarse_levels_and_transfer(n, orders, faces):
+    """Coarse operators on the fine quadrature equal the Galerkin products P^T K P;
+    prolongation/restriction equal the oracle's interpolation matrix and its transpose."""
+    print_case("coarse_levels", n=n, orders=orders, faces=faces)
+    m, H = _setup(n, orders[0], faces=faces, orders=orders)
+    u = inputs.config1_u(m, amplitude=0.05)
+    H.fine.residual(_dev(u), store_state=True)
+    H.fine.state_cast_f32()
+    Ps, Ks = _levels_oracle(m, H, u, faces)
+    from paper_2204_01722_amd.binding import hpmg_prolong_add, hpmg_restrict
+    for l in range(1, len(orders)):
+        opc, opf = H.ops[l], H.ops[l - 1]
+        mc = None if H.masks[l] is None else H.masks[l].reshape(-1).astype(float)
+        mf = None if H.masks[l - 1] is None else H.masks[l - 1].reshape(-1).astype(float)
+        frc = 1.0 if mc is None else 1.0 - mc
+        frf = 1.0 if mf is None else 1.0 - mf
+        x = inputs.random_vector(opc.n_nodes, 10 + l)
+        Kc = fem.apply_bc(Ks[l], H.masks[l])
+        assert rel(t2n(opc.jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
+        assert rel(t2n(opc.jacobian(_dev(x).float(), "f32")), Kc @ x.reshape(-1)) < TOL32
+        assert rel(t2n(opc.diagonal("f64")), Kc.diagonal()) < TOL64
+        # prolong_add: y += M_f P M_c x
+        y0 = inputs.random_vector(opf.n_nodes, 20 + l)
+        yt = _dev(y0.copy())
+        hpmg_prolong_add(opc, opf, _dev(x), yt)
+        ref = y0.reshape(-1) + frf * (Ps[l - 1] @ (frc * x.reshape(-1)))
+        assert rel(t2n(yt), ref) < TOL64
+        yt32 = _dev(y0.copy()).float()
+        hpmg_prolong_add(opc, opf, _dev(x).float(), yt32, "f32")
+        assert rel(t2n(yt32), ref) < TOL32
+        # restrict: r_c = M_c P^T M_f r_f
+        rf = inputs.random_vector(opf.n_nodes, 30 + l)
+        rc = hpmg_restrict(opf, opc, _dev(rf))
+        ref = frc * (Ps[l - 1].T @ (frf * rf.reshape(-1)))
+        assert rel(t2n(rc), ref) < TOL64
+
+
+def test_energy_and_flags():
+    import torch
+    print_case("energy")
+    m, H = _setup(3, 2, jitter=0.05)
+    d = fem.make_disc(m.coords, m.elem_nodes, 3)
+    u = inputs.config1_u(m, amplitude=0.05)
+    psi = float(H.fine.energy(_dev(u)))
+    ref = fem.energy(d, u, MU, LAM)
+    assert abs(psi - ref) <= 1e-12 * abs(ref)
+    # a displacement that inverts elements sets the flag (reported, not raised)
+    bad = -3.0 * m.coords
+    H.fine.residual(_dev(bad), store_state=False)
+    torch.cuda.synchronize()
+    assert H.fine.query_flags() & 1
+
+
+def test_inverted_geometry_flag():
+    print_case("inverted_geometry")
+    from paper_2204_01722_amd.problem import Hierarchy
+    m = inputs.box_mesh(2, 2, jitter=0.0)
+    c = m.coords.copy()
+    c[m.elem_nodes[0, 13]] += np.array([2.0, 0.0, 0.0])
+    m.coords = c
+    H = Hierarchy(m, [2])
+    assert H.fine.query_flags() & 1
+
+
+@pytest.mark.parametrize("mode", ["stored", "recompute"])
+def test_vjp(mode):
+    print_case("vjp", mode=mode)
+    m = inputs.box_mesh(3, 2, jitter=0.05)
+    mu_e, lam_e = inputs.loguniform_materials(m.n_elem, seed=4)
+    faces = {"x0": (1, 1, 1)}
+    m, H = _setup(3, 2, faces=faces, mu_e=mu_e, lam_e=lam_e)
+    d = fem.make_disc(m.coords, m.elem_nodes, 3)
+    mask = inputs.face_mask(m, faces)
+    u = inputs.config1_u(m, amplitude=0.05)
+    w = inputs.random_vector(m.n_nodes, 5)
+    H.fine.residual(_dev(u), store_state=True)
+    ub, mub, lamb = H.fine.residual_vjp(_dev(u), _dev(w), mode=mode)
+    ub_ref, mub_ref, lamb_ref = fem.residual_vjp(d, u, w, mu_e, lam_e, mask)
+    assert rel(t2n(ub), ub_ref) < TOL64
+    assert rel(t2n(mub), mub_ref) < TOL64
+    assert rel(t2n(lamb), lamb_ref) < TOL64
+
+
+@pytest.mark.parametrize("n,p", [(43, 2), (34, 4)])
+def test_full_size_sampled(n, p):
+    """The benchmark workloads (Q2 on 43^3 and Q4 on 34^3 jittered boxes, maximum
+    stretch 1.3) checked on sampled nodes, each against an oracle run over exactly the
+    elements that touch it; plus stored == recompute and FP32 on the whole vector."""
+    import torch
+    print_case("full_size", n=n, p=p)
+    m, H = _setup(n, p, jitter=0.05)
+    op = H.fine
+    u = inputs.stretch_field(m, 1.3)
+    du = inputs.random_vector(m.n_nodes, 3)
+    ut, dut = _dev(u), _dev(du)
+    r = t2n(op.residual(ut, store_state=True))
+    y = t2n(op.jacobian(dut, "f64", "stored"))
+    y2 = t2n(op.jacobian(dut, "f64", "recompute", u=ut))
+    assert rel(y2, y) < 1e-13
+    op.state_cast_f32()
+    y32 = t2n(op.jacobian(dut.float(), "f32", "stored"))
+    assert rel(y32, y) < TOL32
+    assert op.query_flags() == 0
+    rng = np.random.default_rng(99)
+    nodes = rng.choice(m.n_nodes, 48, replace=False)
+    els = incident_elements(m.elem_nodes, nodes)
+    d = fem.make_disc(m.coords, m.elem_nodes[els], m.P)
+    r_ref = fem.residual(d, u, MU, LAM)[nodes]
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM)[nodes]
+    assert rel(r[nodes], r_ref) < TOL64
+    assert rel(y[nodes], y_ref) < TOL64
+    torch.cuda.synchronize()
