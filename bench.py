@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: matrix-free Neo-Hookean Jacobian apply on one MI355X.
+
+Workload (the operator-at-scale configuration): jittered unit-cube box meshes with a
+smooth displacement of maximum stretch 1.3, E = 1, nu = 0.3,
+  * Q4 (P = 5 nodes, 5^3 Gauss points) on 34^3 elements: 7,714,059 DoF  (headline)
+  * Q2 (P = 3, 3^3 points) on 43^3 elements: 1,975,509 DoF.
+A timed "step" is one FP64 Jacobian apply y = J(u) du from the stored 17-scalar
+linearisation (gather, sum-factorised gradient, pointwise tangent, transpose, scatter),
+inputs resident in HBM.  The JSON line also carries Q2 / FP32 / recompute variants,
+the residual, the roofline of the apply kernel, an FP64-vs-mixed p-multigrid solve,
+and the CPU oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 10] [--no-cpu] [--no-solve] [--only-headline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def algorithmic_bytes(E, P, Q, N, word, nstate=17, nvec=2):
+    """Bytes each apply must move once: the per-point linearisation, the input and
+    output L-vectors, and the int32 element-to-node map."""
+    return E * Q ** 3 * nstate * word + nvec * 3 * N * word + 4 * E * P ** 3
+
+
+def time_op(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        fn()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps  # ms
+
+
+def copy_bandwidth(nbytes=2 << 30):
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    s = torch.cuda.current_stream()
+    ms = time_op(lambda: b.copy_(a), 10, 3, s)
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+class Workload:
+    def __init__(self, n, p, device="cuda"):
+        import torch
+        from paper_2204_01722_amd import inputs
+        from paper_2204_01722_amd.problem import Hierarchy
+        self.n, self.p = n, p
+        self.mesh = inputs.box_mesh(n, p, jitter=0.05, seed=2204)
+        self.H = Hierarchy(self.mesh, [p])
+        self.op = self.H.fine
+        self.u_np = inputs.stretch_field(self.mesh, 1.3)
+        self.du_np = inputs.random_vector(self.mesh.n_nodes, 3)
+        self.u = torch.from_numpy(self.u_np).to(device)
+        self.du = torch.from_numpy(self.du_np).to(device)
+        self.du32 = self.du.float()
+        self.r = self.op.residual(self.u, store_state=True)
+        self.op.state_cast_f32()
+        self.y = torch.empty_like(self.du)
+        self.y32 = torch.empty_like(self.du32)
+        self.E, self.P, self.Q, self.N = self.mesh.n_elem, p + 1, p + 1, self.mesh.n_nodes
+        self.dof = 3 * self.N
+        if self.op.query_flags():
+            raise RuntimeError("device flags set during setup")
+
+    def apply(self, prec="f64", mode="stored"):
+        if prec == "f64":
+            return lambda: self.op.jacobian(self.du, "f64", mode, u=self.u, out=self.y)
+        return lambda: self.op.jacobian(self.du32, "f32", mode, u=self.u, out=self.y32)
+
+    def residual(self):
+        return lambda: self.op.residual(self.u, store_state=True, out=self.r)
+
+
+def cpu_baseline(wl, target_s=15.0):
+    """The oracle's matrix-free Jacobian apply (dense element tables, FP64, numpy) on a
+    bounded sample of the workload's elements; rate scaled to DoF of the full mesh."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fem
+    from paper_2204_01722_amd import inputs
+    mu, lam = inputs.lame(1.0, 0.3)
+    m = wl.mesh
+    with threadpool_limits(limits=1):
+        k = 32
+        d = fem.make_disc(m.coords, m.elem_nodes[:k], m.P)
+        t0 = time.perf_counter()
+        fem.jacobian_apply(d, wl.u_np, wl.du_np, mu, lam, chunk=512)
+        per_el = (time.perf_counter() - t0) / k
+        k = int(min(m.n_elem, max(32, (target_s / 3.0) / per_el)))
+        d = fem.make_disc(m.coords, m.elem_nodes[:k], m.P)
+        reps = max(1, int(round(target_s / (per_el * k))))
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fem.jacobian_apply(d, wl.u_np, wl.du_np, mu, lam, chunk=512)
+        dt = (time.perf_counter() - t0) / reps
+    frac = k / m.n_elem
+    rate = wl.dof * frac / dt / 1e9
+    return {"value": rate, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} of {m.n_elem} elements of the Q{wl.p} {wl.n}^3 mesh, FP64 Jacobian apply "
+                      f"(dense element tables, numpy, 1 thread), {reps} repeats of {dt:.3f} s; "
+                      f"rate = DoF x sampled fraction / time"}
+
+
+def pmg_solve(n=12, p=4, steps=2, total_disp=0.5):
+    """FP64 vs mixed-precision p-MG Newton solve (Q4 -> Q2 -> Q1, Chebyshev degree 3,
+    Jacobi-PCG coarse solve to 1e-3, FCG in FP64, Newton to 1e-8), displacement of the
+    x = 1 face by `total_disp` (first `steps` of 5 load steps), x = 0 clamped."""
+    import torch
+    from paper_2204_01722_amd import inputs
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(n, p, jitter=0.05, seed=2204)
+    lift = torch.from_numpy(inputs.affine_lifting(m, (total_disp * steps / 5.0, 0.0, 0.0))).cuda()
+    out = {"workload": f"Q4->Q2->Q1 on {n}^3 jittered box, {3 * m.n_nodes} DoF, {steps} load steps "
+                       f"of x-face displacement {total_disp / 5:.2f}", "dof": 3 * m.n_nodes}
+    us = {}
+    for prec in ("f64", "f32"):
+        H = Hierarchy(m, [p, 2, 1], faces=faces)
+        mg = PMG(H.ops, precision=prec, cheb_degree=3, coarse_rtol=1e-3)
+        u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+        seeds = H.seeds(7)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, st = mg.newton(u, lift, steps, seeds, rtol=1e-8, lin_rtol=1e-3)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = "fp64" if prec == "f64" else "mixed"
+        out[key] = {"seconds": dt, **st}
+        us[key] = u.clone()
+        del mg, H
+    out["rel_diff_mixed_vs_fp64"] = float(torch.linalg.norm(us["mixed"] - us["fp64"]) /
+                                          torch.linalg.norm(us["fp64"]))
+    out["speedup_mixed"] = out["fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--only-headline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    print("[bench] building Q4 34^3 workload", file=sys.stderr, flush=True)
+    q4 = Workload(34, 4)
+    ms = time_op(q4.apply("f64", "stored"), args.steps, args.warmup, stream)
+    value = q4.dof / (ms * 1e-3) / 1e9
+    nbytes = algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 8)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    print(f"[bench] Q4 f64 stored: {ms:.4f} ms, {value:.2f} GDoF/s", file=sys.stderr, flush=True)
+
+    variants = {}
+    if not args.only_headline:
+        for prec, mode in (("f32", "stored"), ("f64", "recompute"), ("f32", "recompute")):
+            t = time_op(q4.apply(prec, mode), args.steps, args.warmup, stream)
+            variants[f"q4_{prec}_{mode}"] = {"ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9}
+        t = time_op(q4.residual(), max(5, args.steps // 5), 2, stream)
+        variants["q4_residual_f64"] = {"ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9}
+        variants["q4_f32_stored"]["hbm_frac"] = (algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 4) /
+                                                 (variants["q4_f32_stored"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS)
+        print("[bench] building Q2 43^3 workload", file=sys.stderr, flush=True)
+        q2 = Workload(43, 2)
+        for prec, mode in (("f64", "stored"), ("f32", "stored"), ("f64", "recompute")):
+            t = time_op(q2.apply(prec, mode), args.steps, args.warmup, stream)
+            v = {"ms": t, "GDoF/s": q2.dof / (t * 1e-3) / 1e9}
+            if mode == "stored":
+                v["hbm_frac"] = (algorithmic_bytes(q2.E, q2.P, q2.Q, q2.N, 8 if prec == "f64" else 4) /
+                                 (t * 1e-3) / 1e9 / HBM_PEAK_GBPS)
+            variants[f"q2_{prec}_{mode}"] = v
+        del q2
+        variants["hbm_copy_GBps"] = copy_bandwidth()
+        print(f"[bench] variants done", file=sys.stderr, flush=True)
+
+    solve = None
+    if not args.no_solve and not args.only_headline:
+        print("[bench] p-MG solve FP64 vs mixed", file=sys.stderr, flush=True)
+        solve = pmg_solve()
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(q4)
+
+    out = {
+        "metric": "GDoF/s Neo-Hookean Jacobian apply (Q2/Q4, fp64 vs fp32) + p-MG solve time",
+        "value": value,
+        "unit": "GDoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Q4 (P=5 GLL nodes, 5^3 Gauss points) on a 34^3 jittered unit box, "
+                               "7,714,059 DoF, stored 17-scalar FP64 Jacobian apply, max stretch 1.3, "
+                               "E=1, nu=0.3", "global_batch": 1, "seq_len": 0, "parallelism": "none"},
+        "roofline": {"bound": "hbm", "kernel": "k_jacobian_stored<double,5,5> + output init",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "algorithmic_bytes_per_launch": nbytes},
+        "variants": variants,
+        "pmg_solve": solve,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -13,6 +13,8 @@
 // tile is one contiguous, coalesced sweep.  Dirichlet flags ride in the top bits of the
 // element-to-node map, so masking costs no extra memory traffic.
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 #include "common.h"
 
@@ -250,6 +252,16 @@ __device__ __forceinline__ void adjoint_qf(const T (&C)[3][3], const T (&A)[3][3
     for (int a = 0; a < 3; ++a) f[i][a] = W * (s[i][0] * A[a][0] + s[i][1] * A[a][1] + s[i][2] * A[a][2]);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Give
+// every XCD a contiguous range of tiles so neighbouring elements (which share nodes,
+// hence gathered values and atomic targets) run under the same L2.
+__device__ __forceinline__ int64_t xcd_tile() {
+  constexpr unsigned NX = 8;
+  const unsigned b = blockIdx.x, G = gridDim.x;
+  const unsigned m = G / NX, r = G % NX, x = b % NX, j = b / NX;
+  return (int64_t)x * m + (x < r ? x : r) + j;
+}
+
 __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
   return mu_e ? mu_e[e] : mu0;
 }
@@ -257,6 +269,30 @@ __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t
 template <typename T>
 __device__ __forceinline__ void load_tables(T *dst, const T *__restrict__ src, int off, int n, int t, int nt) {
   for (int i = t; i < n; i += nt) dst[i] = src[off + i];
+}
+
+// Loads the three components of a node (all issued before any is used) and writes them
+// to LDS as [c][P^3]; constrained components become zero when `masked`.
+template <typename S, typename T>
+__device__ __forceinline__ void gather_node(const S *__restrict__ v, uint32_t w, bool masked, T *a, int q,
+                                            int P3) {
+  const S *p = v + (int64_t)(w & EMAP_ID_MASK) * 3;
+  const S x0 = p[0], x1 = p[1], x2 = p[2];
+  a[q] = (masked && ((w >> EMAP_BC_SHIFT) & 1u)) ? T(0) : (T)x0;
+  a[P3 + q] = (masked && ((w >> (EMAP_BC_SHIFT + 1)) & 1u)) ? T(0) : (T)x1;
+  a[2 * P3 + q] = (masked && ((w >> (EMAP_BC_SHIFT + 2)) & 1u)) ? T(0) : (T)x2;
+}
+
+// Adds the three components of a node from LDS [c][P^3] into v (skipping constrained
+// components when `masked`).
+template <typename T>
+__device__ __forceinline__ void scatter_node(T *__restrict__ v, uint32_t w, bool masked, const T *a, int q,
+                                             int P3) {
+  const T x0 = a[q], x1 = a[P3 + q], x2 = a[2 * P3 + q];
+  T *p = v + (int64_t)(w & EMAP_ID_MASK) * 3;
+  if (!(masked && ((w >> EMAP_BC_SHIFT) & 1u))) atomic_add(p, x0);
+  if (!(masked && ((w >> (EMAP_BC_SHIFT + 1)) & 1u))) atomic_add(p + 1, x1);
+  if (!(masked && ((w >> (EMAP_BC_SHIFT + 2)) & 1u))) atomic_add(p + 2, x2);
 }
 
 // ------------------------------------------------------------------------------------
@@ -274,7 +310,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict_
   __shared__ T sB[Q * P], sD[Q * Q], sW[Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
@@ -295,7 +332,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict_
   T Di[3][3];
   inv3(G, det, Di);  // Di[k][J] = dxi_k / dX_J
   const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
-  double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+  double *g = geo + tile * NGEO * NQ + tq;
   g[0] = sW[q1] * sW[q2] * sW[q3] * det;
 #pragma unroll
   for (int k = 0; k < 3; ++k)
@@ -318,27 +355,31 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
   __shared__ T sB[Q * P], sD[Q * Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
+  uint32_t w = 0;
+  if (live && q < P3) w = emap[e * P3 + q];
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
   T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  if (live && q < P3) {
-    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
+  if (live && q < P3) gather_node(u, w, false, a, q, P3);
+  T gv[NGEO];
+  if (live) {
+    const double *g = geo + tile * NGEO * NQ + tq;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a[c * P3 + q] = u[(int64_t)node * 3 + c];
+    for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
   }
   __syncthreads();
   interp<T, P, Q, 3>(a, b, sB, q, live);
   if (live) {
     T G[3][3], D[3][3];
     grad_q<T, Q, 3>(b, sD, q, G);
-    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
-    const T W = g[0];
+    const T W = gv[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+      for (int J = 0; J < 3; ++J) D[k][J] = gv[1 + k * 3 + J];
     const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
     Kin<T> k;
     kinematics(G, D, mu, lam, k);
@@ -350,7 +391,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
     if (state) {
-      double *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+      double *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
@@ -365,13 +406,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    const uint32_t w = emap[e * P3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&r[(int64_t)node * 3 + c], a[c * P3 + q]);
-  }
+  if (live && q < P3) scatter_node(r, w, true, a, q, P3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -387,32 +422,36 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
   __shared__ T sB[Q * P], sD[Q * Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
+  // Issue order matters (the vector-memory counter retires loads in order): tables and
+  // the element map first, then the gathered nodal values, then the linearisation,
+  // which stays in flight while the interpolation stages run in LDS.
+  uint32_t w = 0;
+  if (live && q < P3) w = emap[e * P3 + q];
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
   T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  uint32_t w = 0;
-  if (live && q < P3) {
-    w = emap[e * P3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
+  T sv[NSTATE];
+  if (live && q < P3) gather_node(du, w, true, a, q, P3);
+  if (live) {
+    const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      a[c * P3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : du[(int64_t)node * 3 + c];
+    for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
   }
   __syncthreads();
   interp<T, P, Q, 3>(a, b, sB, q, live);
   if (live) {
     T G[3][3], A[3][3], tau[6];
     grad_q<T, Q, 3>(b, sD, q, G);
-    const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) A[k][j] = s[(k * 3 + j) * NQ];
+      for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
-    const T c = s[15 * NQ], W = s[16 * NQ];
+    for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
+    const T c = sv[15], W = sv[16];
     const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
     T f[3][3];
     jacobian_qf(G, A, tau, c, W, mu, lam, f);
@@ -425,11 +464,99 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    const uint32_t node = w & EMAP_ID_MASK;
+  if (live && q < P3) scatter_node(y, w, true, a, q, P3);
+}
+
+
+// Persistent, software-pipelined variant of k_jacobian_stored: each workgroup walks a
+// contiguous range of tiles of its XCD and prefetches the next tile's element map,
+// nodal values and linearisation into registers while the current tile is in its LDS
+// stages, so HBM requests stay in flight across the whole element computation.
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored_pipe(
+    const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
+    const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
+    const double *__restrict__ lam_e, T *__restrict__ y, int64_t E, int64_t tiles) {
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[ET * (S0 + S1)];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const unsigned G = gridDim.x, NX = G < 8 ? G : 8, b = blockIdx.x, x = b % NX, j = b / NX;
+  const unsigned nbx = G / NX + (x < G % NX ? 1u : 0u);
+  const int64_t t_end = tiles * (x + 1) / NX;
+  int64_t tile = tiles * x / NX + j;
+  T *a = lds + (tq < NQ ? el : 0) * S0, *bb = lds + ET * S0 + (tq < NQ ? el : 0) * S1;
+  uint32_t w = 0;
+  T d0 = 0, d1 = 0, d2 = 0, sv[NSTATE];
+  {
+    const bool lv = tq < NQ && tile < t_end && tile * ET + el < E;
+    if (lv && q < P3) {
+      w = emap[(tile * ET + el) * P3 + q];
+      const T *p = du + (int64_t)(w & EMAP_ID_MASK) * 3;
+      d0 = p[0];
+      d1 = p[1];
+      d2 = p[2];
+    }
+    if (lv) {
+      const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&y[(int64_t)node * 3 + c], a[c * P3 + q]);
+      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+    }
+  }
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  while (tile < t_end) {
+    const int64_t e = tile * ET + el;
+    const bool live = tq < NQ && e < E;
+    if (live && q < P3) {
+      a[q] = ((w >> EMAP_BC_SHIFT) & 1u) ? T(0) : d0;
+      a[P3 + q] = ((w >> (EMAP_BC_SHIFT + 1)) & 1u) ? T(0) : d1;
+      a[2 * P3 + q] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : d2;
+    }
+    const int64_t next = tile + nbx;
+    const bool live_n = tq < NQ && next < t_end && next * ET + el < E;
+    uint32_t wn = 0;
+    if (live_n && q < P3) wn = emap[(next * ET + el) * P3 + q];
+    __syncthreads();
+    interp<T, P, Q, 3>(a, bb, sB, q, live);
+    if (live) {
+      T G3[3][3], A[3][3], tau[6];
+      grad_q<T, Q, 3>(bb, sD, q, G3);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int jj = 0; jj < 3; ++jj) A[k][jj] = sv[k * 3 + jj];
+#pragma unroll
+      for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
+      const T c = sv[15], W = sv[16];
+      const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+      T f[3][3];
+      jacobian_qf(G3, A, tau, c, W, mu, lam, f);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a[(i * 3 + k) * Q3 + q] = f[i][k];
+    }
+    // the next tile's values are requested now and consumed one iteration later
+    if (live_n && q < P3) {
+      const T *p = du + (int64_t)(wn & EMAP_ID_MASK) * 3;
+      d0 = p[0];
+      d1 = p[1];
+      d2 = p[2];
+    }
+    if (live_n) {
+      const T *s = state + next * NSTATE * NQ + tq;
+#pragma unroll
+      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+    }
+    __syncthreads();
+    grad_t_q<T, Q>(a, sD, q, bb, live);
+    __syncthreads();
+    interp_t<T, P, Q, 3>(bb, a, sB, q, live);
+    if (live && q < P3) scatter_node(y, w, true, a, q, P3);
+    w = wn;
+    tile = next;
   }
 }
 
@@ -446,20 +573,23 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
   __shared__ T sB[Q * P], sD[Q * Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
+  uint32_t w = 0;
+  if (live && q < P3) w = emap[e * P3 + q];
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
   T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  uint32_t w = 0;
   if (live && q < P3) {
-    w = emap[e * P3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
+    gather_node(u, w, false, a, q, P3);
+    gather_node(du, w, true, a + 3 * P3, q, P3);
+  }
+  double gv[NGEO];
+  if (live) {
+    const double *g = geo + tile * NGEO * NQ + tq;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      a[c * P3 + q] = (T)u[(int64_t)node * 3 + c];
-      a[(3 + c) * P3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : du[(int64_t)node * 3 + c];
-    }
+    for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
   }
   __syncthreads();
   interp<T, P, Q, 6>(a, b, sB, q, live);
@@ -473,12 +603,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
         Gu[i][k] = G6[i][k];
         Gd[i][k] = G6[3 + i][k];
       }
-    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
-    const T W = (T)g[0];
+    const T W = (T)gv[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int J = 0; J < 3; ++J) D[k][J] = (T)g[(1 + k * 3 + J) * NQ];
+      for (int J = 0; J < 3; ++J) D[k][J] = (T)gv[1 + k * 3 + J];
     const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
     Kin<T> k;
     kinematics(Gu, D, mu, lam, k);
@@ -493,12 +622,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    const uint32_t node = w & EMAP_ID_MASK;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&y[(int64_t)node * 3 + c], a[c * P3 + q]);
-  }
+  if (live && q < P3) scatter_node(y, w, true, a, q, P3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -519,7 +643,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
   __shared__ T sBB[Q * P], sBG[Q * P], sGG[Q * P];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sBB, tab, TAB_BB, Q * P, tq, NT);
   load_tables(sBG, tab, TAB_BG, Q * P, tq, NT);
@@ -528,7 +653,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
   T K[3][6];  // [component][pair]
   if (live) {
     T A[3][3], tau[6];
-    const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+    const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -597,17 +722,14 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_prolong_add(
   __shared__ T sM[PF * PC];
   __shared__ T lds[2 * ET * S];
   const int tq = threadIdx.x, el = tq / F3, q = tq % F3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sM, tab_c, tab_ctof(PF), PF * PC, tq, NT);
   T *a = lds + (live ? el : 0) * S, *b = lds + ET * S + (live ? el : 0) * S;
-  if (live && q < C3) {
-    const uint32_t w = emap_c[e * C3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      a[c * C3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : xc[(int64_t)node * 3 + c];
-  }
+  uint32_t wf = 0;
+  if (live) wf = emap_f[e * F3 + q];
+  if (live && q < C3) gather_node(xc, emap_c[e * C3 + q], true, a, q, C3);
   __syncthreads();
   stage<T, PC, PC, PC, 0, PF, false, 3>(a, b, sM, q, live);
   __syncthreads();
@@ -616,12 +738,11 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_prolong_add(
   stage<T, PF, PF, PC, 2, PF, false, 3>(a, b, sM, q, live);
   __syncthreads();
   if (live) {
-    const uint32_t w = emap_f[e * F3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
-    const T s = invm[node];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&yf[(int64_t)node * 3 + c], s * b[c * F3 + q]);
+    const T s = invm[wf & EMAP_ID_MASK];
+    b[q] *= s;
+    b[F3 + q] *= s;
+    b[2 * F3 + q] *= s;
+    scatter_node(yf, wf, true, b, q, F3);
   }
 }
 
@@ -634,17 +755,18 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
   __shared__ T sM[PF * PC];
   __shared__ T lds[2 * ET * S];
   const int tq = threadIdx.x, el = tq / F3, q = tq % F3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sM, tab_c, tab_ctof(PF), PF * PC, tq, NT);
   T *a = lds + (live ? el : 0) * S, *b = lds + ET * S + (live ? el : 0) * S;
   if (live) {
     const uint32_t w = emap_f[e * F3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
-    const T s = invm[node];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      a[c * F3 + q] = ((w >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : s * rf[(int64_t)node * 3 + c];
+    const T s = invm[w & EMAP_ID_MASK];
+    gather_node(rf, w, true, a, q, F3);
+    a[q] *= s;
+    a[F3 + q] *= s;
+    a[2 * F3 + q] *= s;
   }
   __syncthreads();
   stage<T, PF, PF, PF, 2, PC, true, 3>(a, b, sM, q, live);
@@ -653,13 +775,7 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
   __syncthreads();
   stage<T, PF, PC, PC, 0, PC, true, 3>(a, b, sM, q, live);
   __syncthreads();
-  if (live && q < C3) {
-    const uint32_t w = emap_c[e * C3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&rc[(int64_t)node * 3 + c], b[c * C3 + q]);
-  }
+  if (live && q < C3) scatter_node(rc, emap_c[e * C3 + q], true, b, q, C3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -679,7 +795,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_energy(const uint32_t *__restrict
   __shared__ T sB[Q * P], sD[Q * Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
@@ -695,7 +812,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_energy(const uint32_t *__restrict
   if (live) {
     T G[3][3], D[3][3];
     grad_q<T, Q, 3>(b, sD, q, G);
-    const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+    const double *g = geo + tile * NGEO * NQ + tq;
     const T W = g[0];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -737,7 +854,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
   __shared__ T sB[Q * P], sD[Q * Q];
   __shared__ T lds[ET * (S0 + S1)];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t e = (int64_t)blockIdx.x * ET + el;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
   const bool live = tq < NQ && e < E;
   load_tables(sB, tab, TAB_B, Q * P, tq, NT);
   load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
@@ -765,7 +883,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
     T twoe[6];
     double logJ;
     if (STORED) {
-      const T *s = state + (int64_t)blockIdx.x * NSTATE * NQ + tq;
+      const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -784,7 +902,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
       for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int k = 0; k < 3; ++k) Gu[i][k] = G[NC - 3 + i][k];
-      const double *g = geo + (int64_t)blockIdx.x * NGEO * NQ + tq;
+      const double *g = geo + tile * NGEO * NQ + tq;
       W = g[0];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
@@ -972,12 +1090,59 @@ hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool
   return hipErrorInvalidValue;
 }
 
+// Jacobian kernel flavour: HPMG_JACOBIAN_KERNEL=pipe selects the persistent pipelined
+// kernel, anything else the one-tile-per-workgroup kernel.
+static bool use_pipe() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("HPMG_JACOBIAN_KERNEL");
+    v = (e && std::string(e) == "pipe") ? 1 : 0;
+  }
+  return v == 1;
+}
+
+// Persistent grid: as many workgroups as can be resident at once (at most `tiles`).
+static unsigned persistent_grid(const void *kern, int threads, int64_t tiles) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess || per_cu <= 0)
+    per_cu = 1;
+  int64_t g = (int64_t)cus * per_cu;
+  if (g > tiles) g = tiles;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,
                            void *y, hipStream_t s) {
   const hpmg_op_s &f = op.fine ? *op.fine : op;
   hipError_t e = launch_init_bc(prec, op.N, op.mask, du, y, s);
   if (e != hipSuccess) return e;
-  if (mode == HPMG_STORED) {
+  if (mode == HPMG_STORED && use_pipe()) {
+    if (prec == HPMG_F64) {
+#define X(p, q)                                                                                        \
+  if (op.P == p && op.Q == q) {                                                                        \
+    auto kern = k_jacobian_stored_pipe<double, p, q>;                                                  \
+    const unsigned g = persistent_grid((const void *)kern, QT<q>::NT, op.tiles);                       \
+    kern<<<g, QT<q>::NT, 0, s>>>(op.emap, (const double *)du, f.state64, op.tab64, f.mu, f.lam, f.mu_e, \
+                                 f.lam_e, (double *)y, op.E, op.tiles);                                \
+    return hipGetLastError();                                                                          \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    } else {
+#define X(p, q)                                                                                       \
+  if (op.P == p && op.Q == q) {                                                                       \
+    auto kern = k_jacobian_stored_pipe<float, p, q>;                                                  \
+    const unsigned g = persistent_grid((const void *)kern, QT<q>::NT, op.tiles);                      \
+    kern<<<g, QT<q>::NT, 0, s>>>(op.emap, (const float *)du, f.state32, op.tab32, f.mu, f.lam, f.mu_e, \
+                                 f.lam_e, (float *)y, op.E, op.tiles);                                \
+    return hipGetLastError();                                                                         \
+  }
+      HPMG_PQ_LIST(X)
+#undef X
+    }
+  } else if (mode == HPMG_STORED) {
     if (prec == HPMG_F64) {
 #define X(p, q)                                                                                     \
   if (op.P == p && op.Q == q) {                                                                     \
