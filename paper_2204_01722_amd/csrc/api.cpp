@@ -61,7 +61,7 @@ int fill_tables(hpmg_op_s *op, OpExtra *x) {
 
 // Byte offsets of the workspace parts; the last entry is the total.
 struct Layout {
-  size_t flags, tab64, tab32, emap, inv64, inv32, scratch, geo, st64, st32, total;
+  size_t flags, tab64, tab32, emap, inv64, inv32, scratch, csr_off, csr_inc, evec, geo, st64, st32, total;
 };
 
 Layout layout_of(const hpmg_op_s *op) {
@@ -74,6 +74,10 @@ Layout layout_of(const hpmg_op_s *op) {
   L.inv64 = o; o += align256((size_t)op->N * sizeof(double));
   L.inv32 = o; o += align256((size_t)op->N * sizeof(float));
   L.scratch = o; o += align256(((size_t)op->E + 2 * RED_BLOCKS + 64) * sizeof(double));
+  const size_t nrec = (size_t)op->E * op->P * op->P * op->P;
+  L.csr_off = o; o += align256(((size_t)op->N + 1) * sizeof(int32_t));
+  L.csr_inc = o; o += align256(nrec * sizeof(int32_t));
+  L.evec = o; o += align256(nrec * 3 * sizeof(double));
   const size_t nq = (size_t)op->tiles * op->NQ;
   if (!op->fine) {
     L.geo = o; o += align256(nq * NGEO * sizeof(double));
@@ -207,6 +211,9 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   op->invmult64 = reinterpret_cast<double *>(w + L.inv64);
   op->invmult32 = reinterpret_cast<float *>(w + L.inv32);
   op->scratch = reinterpret_cast<double *>(w + L.scratch);
+  op->csr_off = reinterpret_cast<int32_t *>(w + L.csr_off);
+  op->csr_inc = reinterpret_cast<int32_t *>(w + L.csr_inc);
+  op->evec = reinterpret_cast<double *>(w + L.evec);
   if (!op->fine) {
     op->geo = reinterpret_cast<double *>(w + L.geo);
     op->state64 = reinterpret_cast<double *>(w + L.st64);
@@ -229,6 +236,22 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
     op->ws = nullptr;
     return fail(HPMG_ERR_SHAPE, "bind_workspace: element map holds node ids outside [0, n_nodes)");
   }
+  // Node -> element-record incidence lists (counting sort in record order, so each
+  // node's contributions are always summed in the same order: the assembled result is
+  // bitwise reproducible).  Built once per handle on the host.
+  const int64_t P3 = (int64_t)op->P * op->P * op->P, nrec = op->E * P3;
+  if (nrec >= 0x7fffffffLL) {
+    op->ws = nullptr;
+    return fail(HPMG_ERR_SHAPE, "bind_workspace: too many element-node records (max 2^31 - 1)");
+  }
+  std::vector<int32_t> en(nrec), off(op->N + 1, 0), inc(nrec);
+  HPMG_HIP(hipMemcpy(en.data(), op->elem_nodes, nrec * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int64_t k = 0; k < nrec; ++k) off[en[k] + 1]++;
+  for (int64_t n = 0; n < op->N; ++n) off[n + 1] += off[n];
+  std::vector<int32_t> cur(off.begin(), off.end() - 1);
+  for (int64_t k = 0; k < nrec; ++k) inc[cur[en[k]]++] = (int32_t)k;
+  HPMG_HIP(hipMemcpy(op->csr_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HPMG_HIP(hipMemcpy(op->csr_inc, inc.data(), inc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   return HPMG_OK;
 }
 

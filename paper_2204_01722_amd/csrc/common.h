@@ -72,6 +72,9 @@ struct hpmg_op_s {
   double *invmult64 = nullptr; // 1 / (number of elements sharing the node)
   float *invmult32 = nullptr;
   double *scratch = nullptr;   // reductions
+  int32_t *csr_off = nullptr;  // node -> incidences (element-local records), [N + 1]
+  int32_t *csr_inc = nullptr;  // record index e * P^3 + a, sorted per node, [E * P^3]
+  double *evec = nullptr;      // element output records [E][P^3][3] (FP64 or FP32)
   unsigned *flags = nullptr;
   bool geo_ready = false, state_ready = false, state32_ready = false;
   void *host_extra = nullptr;  // host-side tables and scalars owned by the handle
@@ -109,6 +112,7 @@ hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipS
 hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
                       double *mub, double *lamb, hipStream_t s);
 hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s);
+bool use_atomic_scatter();
 
 // Vector kernels.
 hipError_t launch_init_bc(int prec, int64_t n_nodes, const uint8_t *mask, const void *x, void *y,

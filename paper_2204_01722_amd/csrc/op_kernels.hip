@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <string>
+#include <type_traits>
 
 #include "common.h"
 
@@ -283,6 +284,17 @@ __device__ __forceinline__ void gather_node(const S *__restrict__ v, uint32_t w,
   a[2 * P3 + q] = (masked && ((w >> (EMAP_BC_SHIFT + 2)) & 1u)) ? T(0) : (T)x2;
 }
 
+// Writes the element's nodal result (LDS [c][P^3]) as records [e][a][c] for the
+// node-centric assembly pass.
+template <typename T>
+__device__ __forceinline__ void store_record(T *__restrict__ ev, int64_t e, const T *a, int q, int P3) {
+  T *p = ev + ((int64_t)e * P3 + q) * 3;
+  const T x0 = a[q], x1 = a[P3 + q], x2 = a[2 * P3 + q];
+  p[0] = x0;
+  p[1] = x1;
+  p[2] = x2;
+}
+
 // Adds the three components of a node from LDS [c][P^3] into v (skipping constrained
 // components when `masked`).
 template <typename T>
@@ -348,7 +360,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
     const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ geo,
     const double *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
     const double *__restrict__ lam_e, double *__restrict__ r, double *__restrict__ state,
-    unsigned *__restrict__ flags, int64_t E) {
+    unsigned *__restrict__ flags, double *__restrict__ ev, int64_t E) {
   using T = double;
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
@@ -406,7 +418,12 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) scatter_node(r, w, true, a, q, P3);
+  if (live && q < P3) {
+    if (ev)
+      store_record(ev, e, a, q, P3);
+    else
+      scatter_node(r, w, true, a, q, P3);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -416,7 +433,7 @@ template <typename T, int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, T *__restrict__ y, int64_t E) {
+    const double *__restrict__ lam_e, T *__restrict__ y, T *__restrict__ ev, int64_t E) {
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
   __shared__ T sB[Q * P], sD[Q * Q];
@@ -464,101 +481,14 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) scatter_node(y, w, true, a, q, P3);
-}
-
-
-// Persistent, software-pipelined variant of k_jacobian_stored: each workgroup walks a
-// contiguous range of tiles of its XCD and prefetches the next tile's element map,
-// nodal values and linearisation into registers while the current tile is in its LDS
-// stages, so HBM requests stay in flight across the whole element computation.
-template <typename T, int P, int Q>
-__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored_pipe(
-    const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
-    const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, T *__restrict__ y, int64_t E, int64_t tiles) {
-  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
-  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
-  __shared__ T sB[Q * P], sD[Q * Q];
-  __shared__ T lds[ET * (S0 + S1)];
-  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const unsigned G = gridDim.x, NX = G < 8 ? G : 8, b = blockIdx.x, x = b % NX, j = b / NX;
-  const unsigned nbx = G / NX + (x < G % NX ? 1u : 0u);
-  const int64_t t_end = tiles * (x + 1) / NX;
-  int64_t tile = tiles * x / NX + j;
-  T *a = lds + (tq < NQ ? el : 0) * S0, *bb = lds + ET * S0 + (tq < NQ ? el : 0) * S1;
-  uint32_t w = 0;
-  T d0 = 0, d1 = 0, d2 = 0, sv[NSTATE];
-  {
-    const bool lv = tq < NQ && tile < t_end && tile * ET + el < E;
-    if (lv && q < P3) {
-      w = emap[(tile * ET + el) * P3 + q];
-      const T *p = du + (int64_t)(w & EMAP_ID_MASK) * 3;
-      d0 = p[0];
-      d1 = p[1];
-      d2 = p[2];
-    }
-    if (lv) {
-      const T *s = state + tile * NSTATE * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
-    }
-  }
-  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
-  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
-  while (tile < t_end) {
-    const int64_t e = tile * ET + el;
-    const bool live = tq < NQ && e < E;
-    if (live && q < P3) {
-      a[q] = ((w >> EMAP_BC_SHIFT) & 1u) ? T(0) : d0;
-      a[P3 + q] = ((w >> (EMAP_BC_SHIFT + 1)) & 1u) ? T(0) : d1;
-      a[2 * P3 + q] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : d2;
-    }
-    const int64_t next = tile + nbx;
-    const bool live_n = tq < NQ && next < t_end && next * ET + el < E;
-    uint32_t wn = 0;
-    if (live_n && q < P3) wn = emap[(next * ET + el) * P3 + q];
-    __syncthreads();
-    interp<T, P, Q, 3>(a, bb, sB, q, live);
-    if (live) {
-      T G3[3][3], A[3][3], tau[6];
-      grad_q<T, Q, 3>(bb, sD, q, G3);
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-#pragma unroll
-        for (int jj = 0; jj < 3; ++jj) A[k][jj] = sv[k * 3 + jj];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
-      const T c = sv[15], W = sv[16];
-      const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
-      T f[3][3];
-      jacobian_qf(G3, A, tau, c, W, mu, lam, f);
-#pragma unroll
-      for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a[(i * 3 + k) * Q3 + q] = f[i][k];
-    }
-    // the next tile's values are requested now and consumed one iteration later
-    if (live_n && q < P3) {
-      const T *p = du + (int64_t)(wn & EMAP_ID_MASK) * 3;
-      d0 = p[0];
-      d1 = p[1];
-      d2 = p[2];
-    }
-    if (live_n) {
-      const T *s = state + next * NSTATE * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
-    }
-    __syncthreads();
-    grad_t_q<T, Q>(a, sD, q, bb, live);
-    __syncthreads();
-    interp_t<T, P, Q, 3>(bb, a, sB, q, live);
-    if (live && q < P3) scatter_node(y, w, true, a, q, P3);
-    w = wn;
-    tile = next;
+  if (live && q < P3) {
+    if (ev)
+      store_record(ev, e, a, q, P3);
+    else
+      scatter_node(y, w, true, a, q, P3);
   }
 }
+
 
 // ------------------------------------------------------------------------------------
 // a5': Jacobian action recomputing the linearisation from u and the geometry.
@@ -567,7 +497,8 @@ template <typename T, int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
     const uint32_t *__restrict__ emap, const double *__restrict__ u, const T *__restrict__ du,
     const double *__restrict__ geo, const T *__restrict__ tab, double mu0, double lam0,
-    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ y, int64_t E) {
+    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ y, T *__restrict__ ev,
+    int64_t E) {
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
   __shared__ T sB[Q * P], sD[Q * Q];
@@ -622,7 +553,12 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) scatter_node(y, w, true, a, q, P3);
+  if (live && q < P3) {
+    if (ev)
+      store_record(ev, e, a, q, P3);
+    else
+      scatter_node(y, w, true, a, q, P3);
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -1024,7 +960,44 @@ __global__ void k_zero_d(double *__restrict__ x, int64_t n) {
   if (i < n) x[i] = 0.0;
 }
 
+// Node-centric assembly: y[n] = sum of the node's element records, in the fixed order
+// of its incidence list; constrained components take `src` (or zero).
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ inc, const T *__restrict__ ev,
+                                                  const uint8_t *__restrict__ mask, const T *__restrict__ src,
+                                                  T *__restrict__ y) {
+  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t k0 = off[n], k1 = off[n + 1];
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t k = k0; k < k1; ++k) {
+      const T *p = ev + (int64_t)inc[k] * 3;
+      a0 += p[0];
+      a1 += p[1];
+      a2 += p[2];
+    }
+    if (mask) {
+      const uint8_t *m = mask + n * 3;
+      if (m[0]) a0 = src ? src[n * 3] : T(0);
+      if (m[1]) a1 = src ? src[n * 3 + 1] : T(0);
+      if (m[2]) a2 = src ? src[n * 3 + 2] : T(0);
+    }
+    T *o = y + n * 3;
+    o[0] = a0;
+    o[1] = a1;
+    o[2] = a2;
+  }
+}
+
 inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T>
+hipError_t assemble(const hpmg_op_s &op, const T *src, T *y, hipStream_t s) {
+  int64_t g = (op.N + 255) / 256;
+  if (g < 1) g = 1;
+  k_assemble<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src, y);
+  return hipGetLastError();
+}
 
 // ------------------------------------------------------------------------------------
 // (P, Q) dispatch.
@@ -1075,115 +1048,75 @@ hipError_t launch_qdata(const hpmg_op_s &op, const double *X, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// Scatter flavour: HPMG_SCATTER=atomic selects hardware atomics into the output;
+// otherwise element records + the node-centric assembly pass (deterministic).
+bool use_atomic_scatter() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("HPMG_SCATTER");
+    v = (e && std::string(e) == "atomic") ? 1 : 0;
+  }
+  return v == 1;
+}
+
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
-  hipError_t e = launch_init_bc(HPMG_F64, op.N, op.mask, nullptr, r, s);
-  if (e != hipSuccess) return e;
+  const bool atom = use_atomic_scatter();
+  if (atom) {
+    hipError_t e = launch_init_bc(HPMG_F64, op.N, op.mask, nullptr, r, s);
+    if (e != hipSuccess) return e;
+  }
+  double *ev = atom ? nullptr : op.evec;
 #define X(p, q)                                                                                  \
   if (op.P == p && op.Q == q) {                                                                  \
     k_residual<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, op.lam, \
                                                               op.mu_e, op.lam_e, r,              \
-                                                              store ? op.state64 : nullptr, op.flags, op.E); \
-    return hipGetLastError();                                                                    \
+                                                              store ? op.state64 : nullptr, op.flags, ev, op.E); \
+    hipError_t e = hipGetLastError();                                                            \
+    if (e != hipSuccess || atom) return e;                                                       \
+    return assemble<double>(op, nullptr, r, s);                                                  \
   }
   HPMG_PQ_LIST(X)
 #undef X
   return hipErrorInvalidValue;
 }
 
-// Jacobian kernel flavour: HPMG_JACOBIAN_KERNEL=pipe selects the persistent pipelined
-// kernel, anything else the one-tile-per-workgroup kernel.
-static bool use_pipe() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("HPMG_JACOBIAN_KERNEL");
-    v = (e && std::string(e) == "pipe") ? 1 : 0;
+template <typename T, int P, int Q>
+static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode, const double *u, const T *du,
+                              T *y, T *ev, hipStream_t s) {
+  const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
+  const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
+  if (mode == HPMG_STORED) {
+    k_jacobian_stored<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
+                                                                        f.mu_e, f.lam_e, y, ev, op.E);
+  } else {
+    k_jacobian_recompute<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, u, du, op.geo, tab, op.mu,
+                                                                           op.lam, op.mu_e, op.lam_e, y, ev, op.E);
   }
-  return v == 1;
+  return hipGetLastError();
 }
 
-// Persistent grid: as many workgroups as can be resident at once (at most `tiles`).
-static unsigned persistent_grid(const void *kern, int threads, int64_t tiles) {
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0) != hipSuccess || per_cu <= 0)
-    per_cu = 1;
-  int64_t g = (int64_t)cus * per_cu;
-  if (g > tiles) g = tiles;
-  return (unsigned)(g < 1 ? 1 : g);
+template <typename T>
+static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, const T *du, T *y, hipStream_t s) {
+  const hpmg_op_s &f = op.fine ? *op.fine : op;
+  const bool atom = use_atomic_scatter();
+  if (atom) {
+    hipError_t e = launch_init_bc(std::is_same<T, double>::value ? HPMG_F64 : HPMG_F32, op.N, op.mask, du, y, s);
+    if (e != hipSuccess) return e;
+  }
+  T *ev = atom ? nullptr : (T *)op.evec;
+  hipError_t e = hipErrorInvalidValue;
+#define X(p, q) \
+  if (op.P == p && op.Q == q) e = jacobian_pq<T, p, q>(op, f, mode, u, du, y, ev, s);
+  HPMG_PQ_LIST(X)
+#undef X
+  if (e != hipSuccess || atom) return e;
+  return assemble<T>(op, du, y, s);
 }
 
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,
                            void *y, hipStream_t s) {
-  const hpmg_op_s &f = op.fine ? *op.fine : op;
-  hipError_t e = launch_init_bc(prec, op.N, op.mask, du, y, s);
-  if (e != hipSuccess) return e;
-  if (mode == HPMG_STORED && use_pipe()) {
-    if (prec == HPMG_F64) {
-#define X(p, q)                                                                                        \
-  if (op.P == p && op.Q == q) {                                                                        \
-    auto kern = k_jacobian_stored_pipe<double, p, q>;                                                  \
-    const unsigned g = persistent_grid((const void *)kern, QT<q>::NT, op.tiles);                       \
-    kern<<<g, QT<q>::NT, 0, s>>>(op.emap, (const double *)du, f.state64, op.tab64, f.mu, f.lam, f.mu_e, \
-                                 f.lam_e, (double *)y, op.E, op.tiles);                                \
-    return hipGetLastError();                                                                          \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    } else {
-#define X(p, q)                                                                                       \
-  if (op.P == p && op.Q == q) {                                                                       \
-    auto kern = k_jacobian_stored_pipe<float, p, q>;                                                  \
-    const unsigned g = persistent_grid((const void *)kern, QT<q>::NT, op.tiles);                      \
-    kern<<<g, QT<q>::NT, 0, s>>>(op.emap, (const float *)du, f.state32, op.tab32, f.mu, f.lam, f.mu_e, \
-                                 f.lam_e, (float *)y, op.E, op.tiles);                                \
-    return hipGetLastError();                                                                         \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    }
-  } else if (mode == HPMG_STORED) {
-    if (prec == HPMG_F64) {
-#define X(p, q)                                                                                     \
-  if (op.P == p && op.Q == q) {                                                                     \
-    k_jacobian_stored<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                        \
-        op.emap, (const double *)du, f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, (double *)y, op.E); \
-    return hipGetLastError();                                                                       \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    } else {
-#define X(p, q)                                                                                    \
-  if (op.P == p && op.Q == q) {                                                                    \
-    k_jacobian_stored<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                        \
-        op.emap, (const float *)du, f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e, (float *)y, op.E); \
-    return hipGetLastError();                                                                      \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    }
-  } else {
-    if (prec == HPMG_F64) {
-#define X(p, q)                                                                                      \
-  if (op.P == p && op.Q == q) {                                                                      \
-    k_jacobian_recompute<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                      \
-        op.emap, u, (const double *)du, op.geo, op.tab64, op.mu, op.lam, op.mu_e, op.lam_e, (double *)y, op.E); \
-    return hipGetLastError();                                                                        \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    } else {
-#define X(p, q)                                                                                     \
-  if (op.P == p && op.Q == q) {                                                                     \
-    k_jacobian_recompute<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                      \
-        op.emap, u, (const float *)du, op.geo, op.tab32, op.mu, op.lam, op.mu_e, op.lam_e, (float *)y, op.E); \
-    return hipGetLastError();                                                                       \
-  }
-      HPMG_PQ_LIST(X)
-#undef X
-    }
-  }
-  return hipErrorInvalidValue;
+  if (prec == HPMG_F64) return jacobian_t<double>(op, mode, u, (const double *)du, (double *)y, s);
+  return jacobian_t<float>(op, mode, u, (const float *)du, (float *)y, s);
 }
 
 hipError_t launch_diagonal(const hpmg_op_s &op, int prec, void *diag, hipStream_t s) {
