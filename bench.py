@@ -35,6 +35,20 @@ def algorithmic_bytes(E, P, Q, N, word, nstate=17, nvec=2):
     return E * Q ** 3 * nstate * word + nvec * 3 * N * word + 4 * E * P ** 3
 
 
+def measured_traffic():
+    """HBM bytes per apply from the committed counter summary, if it was taken on the
+    current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_jacobian_stored_q4_fp64_34cubed.json")
+    src = os.path.join(ROOT, "paper_2204_01722_amd", "csrc", "op_kernels.hip")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return rec.get("bytes_per_apply")
+
+
 def time_op(fn, steps, warmup, stream):
     import torch
     for _ in range(warmup):
@@ -51,12 +65,14 @@ def time_op(fn, steps, warmup, stream):
 
 
 def copy_bandwidth(nbytes=2 << 30):
+    """Plain streaming kernel of known size (read 2 GiB, write 2 GiB): the achievable
+    bandwidth, and the reference that scales the byte counters of a profiled run."""
     import torch
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
     a.fill_(1.0)
     b = torch.empty_like(a)
     s = torch.cuda.current_stream()
-    ms = time_op(lambda: b.copy_(a), 10, 3, s)
+    ms = time_op(lambda: torch.mul(a, 1.0, out=b), 10, 3, s)
     del a, b
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
@@ -165,6 +181,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--only-headline", action="store_true")
+    ap.add_argument("--pmg-n", type=int, default=16, help="elements per direction of the p-MG solve")
+    ap.add_argument("--pmg-only", action="store_true", help="run only the FP64-vs-mixed p-MG solve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -176,6 +194,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.pmg_only:
+        print(json.dumps({"pmg_solve": pmg_solve(n=args.pmg_n)}))
+        return
 
     print("[bench] building Q4 34^3 workload", file=sys.stderr, flush=True)
     q4 = Workload(34, 4)
@@ -204,6 +225,18 @@ def main():
                                  (t * 1e-3) / 1e9 / HBM_PEAK_GBPS)
             variants[f"q2_{prec}_{mode}"] = v
         del q2
+        # working sets well beyond the 256 MB Infinity Cache
+        for n, p in ((68, 4), (86, 2)):
+            print(f"[bench] building Q{p} {n}^3 workload (cache-busting)", file=sys.stderr, flush=True)
+            wl = Workload(n, p)
+            for prec in ("f64", "f32"):
+                t = time_op(wl.apply(prec, "stored"), max(10, args.steps // 2), 3, stream)
+                variants[f"q{p}_{n}cubed_{prec}_stored"] = {
+                    "ms": t, "dof": wl.dof, "GDoF/s": wl.dof / (t * 1e-3) / 1e9,
+                    "hbm_frac": algorithmic_bytes(wl.E, wl.P, wl.Q, wl.N, 8 if prec == "f64" else 4) /
+                    (t * 1e-3) / 1e9 / HBM_PEAK_GBPS}
+            del wl
+            torch.cuda.empty_cache()
         print(f"[bench] variants done", file=sys.stderr, flush=True)
     # a plain device copy of known size: achievable bandwidth, and the reference kernel
     # that scales the HBM byte counters of a profiled run
@@ -212,7 +245,7 @@ def main():
     solve = None
     if not args.no_solve and not args.only_headline:
         print("[bench] p-MG solve FP64 vs mixed", file=sys.stderr, flush=True)
-        solve = pmg_solve()
+        solve = pmg_solve(n=args.pmg_n)
 
     cpu = None
     if not args.no_cpu:
@@ -237,7 +270,7 @@ def main():
                                "E=1, nu=0.3", "global_batch": 1, "seq_len": 0, "parallelism": "none"},
         "roofline": {"bound": "hbm", "kernel": "k_jacobian_stored<double,5,5> + k_assemble<double> (one apply)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": nbytes},
         "variants": variants,
         "pmg_solve": solve,

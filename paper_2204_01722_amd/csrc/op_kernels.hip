@@ -110,17 +110,19 @@ __device__ __forceinline__ void grad_t_q(const T *f, const T *sD, int q, T *out,
   constexpr int Q3 = Q * Q * Q;
   if (!live || q >= Q3) return;
   const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
+  T acc[3] = {0, 0, 0};
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    T acc = 0;
+  for (int j = 0; j < Q; ++j) {
+    const T d1 = sD[j * Q + q1], d2 = sD[j * Q + q2], d3 = sD[j * Q + q3];
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      acc += sD[j * Q + q1] * f[(c * 3 + 0) * Q3 + j + Q * (q2 + Q * q3)];
-      acc += sD[j * Q + q2] * f[(c * 3 + 1) * Q3 + q1 + Q * (j + Q * q3)];
-      acc += sD[j * Q + q3] * f[(c * 3 + 2) * Q3 + q1 + Q * (q2 + Q * j)];
+    for (int c = 0; c < 3; ++c) {
+      acc[c] += d1 * f[(c * 3 + 0) * Q3 + j + Q * (q2 + Q * q3)];
+      acc[c] += d2 * f[(c * 3 + 1) * Q3 + q1 + Q * (j + Q * q3)];
+      acc[c] += d3 * f[(c * 3 + 2) * Q3 + q1 + Q * (q2 + Q * j)];
     }
-    out[c * Q3 + q] = acc;
   }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) out[c * Q3 + q] = acc[c];
 }
 
 template <typename T>

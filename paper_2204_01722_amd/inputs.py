@@ -190,19 +190,23 @@ def config1_u(mesh: BoxMesh, amplitude: float = 0.01, noise_std: float = 1e-4,
     return amplitude * sinusoid(mesh.coords, mesh.L) + rng.normal(0.0, noise_std, (mesh.n_nodes, 3))
 
 
-def calibrated_amplitude(mesh: BoxMesh, target_stretch: float = 1.3) -> float:
-    """Amplitude ``A`` such that the largest singular value of ``I + A grad(s)`` over
-    the mesh nodes equals ``target_stretch`` (bisection on the analytic field)."""
-    g = sinusoid_grad(mesh.coords, mesh.L)
+def calibrated_amplitude(mesh: BoxMesh, target_stretch: float = 1.3, samples: int = 33) -> float:
+    """Amplitude ``A`` such that the largest singular value of ``I + A grad(s)`` over a
+    uniform ``samples^3`` grid of the box equals ``target_stretch`` (bisection on the
+    analytic field; independent of the mesh resolution)."""
+    axes = [np.linspace(0.0, mesh.L[d], samples) for d in range(3)]
+    X = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1).reshape(-1, 3)
+    g = sinusoid_grad(X, mesh.L)
     eye = np.eye(3)[None]
 
     def stretch(a):
-        return np.linalg.svd(eye + a * g, compute_uv=False)[:, 0].max()
+        F = eye + a * g
+        return np.sqrt(np.linalg.eigvalsh(np.einsum("nki,nkj->nij", F, F))[:, -1].max())
 
     lo, hi = 0.0, 1.0
     while stretch(hi) < target_stretch:
         hi *= 2.0
-    for _ in range(60):
+    while hi - lo > 1e-10 * hi:
         mid = 0.5 * (lo + hi)
         if stretch(mid) < target_stretch:
             lo = mid
