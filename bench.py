@@ -164,7 +164,7 @@ def pmg_solve(n=16, p=4, steps=5, total_disp=0.5):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         key = "fp64" if prec == "f64" else "mixed"
-        out[key] = {"seconds": dt, **st}
+        out[key] = {"seconds": dt, **st, **mg.stats()}
         us[key] = u.clone()
         del mg, H
     out["rel_diff_mixed_vs_fp64"] = float(torch.linalg.norm(us["mixed"] - us["fp64"]) /

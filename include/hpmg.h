@@ -210,6 +210,11 @@ int hpmg_mg_vcycle(hpmg_mg mg, const double *r, double *z, void *stream);
 /* lambda_max estimate of a level and the last coarse-solve iteration count. */
 int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its);
 
+/* Counters since creation (host only): out[0] V-cycles, out[1] coarse-solve
+ * iterations, out[2] setups, out[3 + l] stored-mode operator applies on level l
+ * (l < 8; smoothing, residuals, coarse iterations and eigenvalue estimates). */
+int hpmg_mg_stats(hpmg_mg mg, int64_t *out);
+
 /* a14: flexible CG (FP64) on the fine operator, preconditioned by one V-cycle of
  * `mg` (or Jacobi with the fine FP64 diagonal if mg is NULL and diag given).
  * Solves J x = b from the x passed in; stops at ||b - Jx|| <= rtol ||b - J x0||.

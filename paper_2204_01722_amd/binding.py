@@ -79,6 +79,7 @@ _SIGS = {
     "hpmg_mg_setup": ([_VP, _VP, _VP], _I),
     "hpmg_mg_vcycle": ([_VP, _VP, _VP, _VP], _I),
     "hpmg_mg_info": ([_VP, _I, C.POINTER(_D), C.POINTER(_I)], _I),
+    "hpmg_mg_stats": ([_VP, _VP], _I),
     "hpmg_fcg_solve": ([_VP, _VP, _VP, _VP, _D, _I, C.POINTER(_I), C.POINTER(_D), _VP], _I),
     "hpmg_newton_default_params": ([C.POINTER(NewtonParams)], None),
     "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
@@ -373,6 +374,13 @@ class PMG:
         lam, its = C.c_double(), C.c_int()
         _check(lib().hpmg_mg_info(self.h, level, C.byref(lam), C.byref(its)))
         return float(lam.value), int(its.value)
+
+    def stats(self):
+        arr = (C.c_int64 * 11)()
+        _check(lib().hpmg_mg_stats(self.h, C.cast(arr, C.c_void_p)))
+        v = list(arr)
+        return {"vcycles": v[0], "coarse_its": v[1], "setups": v[2],
+                "applies_per_level": v[3:3 + len(self.levels)]}
 
     def fcg(self, b, x=None, rtol=1e-8, maxit=500):
         x = torch.zeros_like(b) if x is None else x

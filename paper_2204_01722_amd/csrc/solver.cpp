@@ -38,6 +38,9 @@ struct hpmg_mg_s {
   double *nF = nullptr, *ndu = nullptr, *nut = nullptr;
   int last_coarse_its = 0;
   int setup_done = 0;
+  // counters since creation: V-cycles, coarse iterations, operator applies per level
+  int64_t n_vcycles = 0, n_coarse_its = 0, n_setups = 0;
+  int64_t n_applies[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -84,8 +87,10 @@ int read_scalars(hpmg_mg_s *mg, int count, hipStream_t s) {
   return HPMG_OK;
 }
 
-int apply(const Level &L, int prec, const void *in, void *out, hipStream_t s) {
+int apply(hpmg_mg_s *mg, const Level &L, int prec, const void *in, void *out, hipStream_t s) {
   HPMG_HIP(launch_jacobian(*L.op, prec, HPMG_STORED, nullptr, in, out, s));
+  const size_t l = &L - mg->lv.data();
+  if (l < 8) mg->n_applies[l]++;
   return HPMG_OK;
 }
 
@@ -139,7 +144,7 @@ int pcg(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, hi
   const int limit = fixed > 0 ? fixed : maxit;
   int its = 0;
   while (its < limit) {
-    if ((st = apply(L, prec, L.d, L.t, s))) return st;
+    if ((st = apply(mg, L, prec, L.d, L.t, s))) return st;
     HPMG_HIP(launch_dot(prec, L.n, L.d, L.t, mg->red, mg->scal, s));
     if ((st = read_scalars(mg, 1, s))) return st;
     const double pq = mg->host[0];
@@ -172,11 +177,11 @@ int chebyshev(hpmg_mg_s *mg, Level &L, int prec, bool x_zero, hipStream_t s) {
   if (x_zero) {
     HPMG_HIP(launch_cheb_first(prec, L.n, L.dinv, L.b, nullptr, L.r, L.d, L.x, 1.0 / theta, s));
   } else {
-    if ((st = apply(L, prec, L.x, L.t, s))) return st;
+    if ((st = apply(mg, L, prec, L.x, L.t, s))) return st;
     HPMG_HIP(launch_cheb_first(prec, L.n, L.dinv, L.b, L.t, L.r, L.d, L.x, 1.0 / theta, s));
   }
   for (int k = 1; k < mg->prm.cheb_degree; ++k) {
-    if ((st = apply(L, prec, L.d, L.t, s))) return st;
+    if ((st = apply(mg, L, prec, L.d, L.t, s))) return st;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     HPMG_HIP(launch_cheb_step(prec, L.n, L.dinv, L.r, L.t, L.d, L.x, rho_new * rho, 2.0 * rho_new / delta, s));
     rho = rho_new;
@@ -193,11 +198,12 @@ int cycle(hpmg_mg_s *mg, int l, hipStream_t s) {
     st = pcg(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its, s, &its, nullptr,
              nullptr);
     mg->last_coarse_its = its;
+    mg->n_coarse_its += its;
     return st;
   }
   Level &C = mg->lv[l + 1];
   if ((st = chebyshev(mg, L, prec, true, s))) return st;
-  if ((st = apply(L, prec, L.x, L.t, s))) return st;
+  if ((st = apply(mg, L, prec, L.x, L.t, s))) return st;
   HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, -1.0, L.t, L.r, s));
   HPMG_HIP(launch_restrict(*L.op, *C.op, prec, L.r, C.b, s));
   if ((st = cycle(mg, l + 1, s))) return st;
@@ -207,6 +213,7 @@ int cycle(hpmg_mg_s *mg, int l, hipStream_t s) {
 
 int vcycle(hpmg_mg_s *mg, const double *r, double *z, hipStream_t s) {
   int st;
+  mg->n_vcycles++;
   Level &L = mg->lv[0];
   const int prec = prec_of(mg);
   if (prec == HPMG_F64)
@@ -259,6 +266,7 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
     if (!(L.lam > 0.0) || !std::isfinite(L.lam)) return fail(HPMG_ERR_BREAKDOWN, "mg_setup: bad lambda_max");
   }
   mg->setup_done = 1;
+  mg->n_setups++;
   return HPMG_OK;
 }
 
@@ -408,6 +416,15 @@ int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its
   if (level < 0 || level >= (int)mg->lv.size()) return fail(HPMG_ERR_ARG, "mg_info: bad level");
   if (lambda_max) *lambda_max = mg->lv[level].lam;
   if (last_coarse_its) *last_coarse_its = mg->last_coarse_its;
+  return HPMG_OK;
+}
+
+int hpmg_mg_stats(hpmg_mg mg, int64_t *out) {
+  if (!mg || !out) return fail(HPMG_ERR_ARG, "mg_stats: null argument");
+  out[0] = mg->n_vcycles;
+  out[1] = mg->n_coarse_its;
+  out[2] = mg->n_setups;
+  for (int l = 0; l < 8; ++l) out[3 + l] = mg->n_applies[l];
   return HPMG_OK;
 }
 
