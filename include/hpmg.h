@@ -137,6 +137,15 @@ int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void 
  *   factors (fine operators only, precision HPMG_F64 or HPMG_F32). */
 int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, const void *du,
                         void *y, void *stream);
+/* Order-1 coarse operators only (Pc = 2): builds the dense 24 x 24 element matrices
+ * of this level's Galerkin operator from the fine operator's stored linearisation
+ * (the element-level triple product B^T D B of Section III-D), in
+ * `precision`.  While the fine linearisation is unchanged, stored-mode applies of this
+ * operator in that precision then read the element matrices (576 scalars per element)
+ * instead of the fine-quadrature linearisation.  A new stored linearisation makes them
+ * stale; applies fall back to the quadrature form until they are rebuilt. */
+int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
+
 /* Casts the stored FP64 linearisation to the FP32 copy used by FP32 applies. */
 int hpmg_state_cast_f32(hpmg_op op, void *stream);
 
@@ -189,6 +198,7 @@ typedef struct {
   int coarse_maxit;     /* its cap (default 10000) */
   int coarse_fixed_its; /* > 0: run exactly this many coarse iterations (tests) */
   int precision;        /* HPMG_F32: smoothing/transfer/coarse solve in FP32 */
+  int coarse_element_matrices; /* 1: order-1 coarsest level applied with element matrices */
 } hpmg_mg_params;
 
 void hpmg_mg_default_params(hpmg_mg_params *p);

@@ -35,7 +35,8 @@ class HpmgError(RuntimeError):
 class MGParams(C.Structure):
     _fields_ = [("cheb_degree", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("lanczos_its", C.c_int), ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
-                ("coarse_fixed_its", C.c_int), ("precision", C.c_int)]
+                ("coarse_fixed_its", C.c_int), ("precision", C.c_int),
+                ("coarse_element_matrices", C.c_int)]
 
 
 class NewtonParams(C.Structure):
@@ -63,6 +64,7 @@ _SIGS = {
     "hpmg_residual": ([_VP, _VP, _VP, _I, _VP], _I),
     "hpmg_jacobian_apply": ([_VP, _I, _I, _VP, _VP, _VP, _VP], _I),
     "hpmg_state_cast_f32": ([_VP, _VP], _I),
+    "hpmg_op_assemble_elements": ([_VP, _I, _VP], _I),
     "hpmg_diagonal": ([_VP, _I, _VP, _VP], _I),
     "hpmg_prolong_add": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
     "hpmg_restrict": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
@@ -265,6 +267,9 @@ class Operator:
     def state_cast_f32(self):
         _check(lib().hpmg_state_cast_f32(self.h, _stream()))
 
+    def assemble_elements(self, precision="f64"):
+        _check(lib().hpmg_op_assemble_elements(self.h, _prec(precision), _stream()))
+
     def diagonal(self, precision="f64"):
         prec = _prec(precision)
         d = self._vec(_dtype(prec))
@@ -328,13 +333,15 @@ class PMG:
     """p-multigrid V-cycle over ``levels`` (fine first), with FCG and Newton drivers."""
 
     def __init__(self, levels, precision="f64", cheb_degree=3, cheb_lo=0.1, cheb_hi=1.1,
-                 lanczos_its=10, coarse_rtol=1e-3, coarse_maxit=10000, coarse_fixed_its=0):
+                 lanczos_its=10, coarse_rtol=1e-3, coarse_maxit=10000, coarse_fixed_its=0,
+                 coarse_element_matrices=True):
         self.levels = list(levels)
         prm = MGParams()
         lib().hpmg_mg_default_params(C.byref(prm))
         prm.cheb_degree, prm.cheb_lo, prm.cheb_hi = cheb_degree, cheb_lo, cheb_hi
         prm.lanczos_its, prm.coarse_rtol, prm.coarse_maxit = lanczos_its, coarse_rtol, coarse_maxit
         prm.coarse_fixed_its, prm.precision = coarse_fixed_its, _prec(precision)
+        prm.coarse_element_matrices = int(bool(coarse_element_matrices))
         self.params = prm
         arr = (C.c_void_p * len(self.levels))(*[op.h.value for op in self.levels])
         h = C.c_void_p()

@@ -61,7 +61,7 @@ int fill_tables(hpmg_op_s *op, OpExtra *x) {
 
 // Byte offsets of the workspace parts; the last entry is the total.
 struct Layout {
-  size_t flags, tab64, tab32, emap, inv64, inv32, scratch, csr_off, csr_inc, evec, geo, st64, st32, total;
+  size_t flags, tab64, tab32, emap, inv64, inv32, scratch, csr_off, csr_inc, evec, elmat, geo, st64, st32, total;
 };
 
 Layout layout_of(const hpmg_op_s *op) {
@@ -78,6 +78,7 @@ Layout layout_of(const hpmg_op_s *op) {
   L.csr_off = o; o += align256(((size_t)op->N + 1) * sizeof(int32_t));
   L.csr_inc = o; o += align256(nrec * sizeof(int32_t));
   L.evec = o; o += align256(nrec * 3 * sizeof(double));
+  L.elmat = o; o += (op->fine && op->P == 2) ? align256((size_t)op->E * 576 * sizeof(double)) : 0;
   const size_t nq = (size_t)op->tiles * op->NQ;
   if (!op->fine) {
     L.geo = o; o += align256(nq * NGEO * sizeof(double));
@@ -214,6 +215,8 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   op->csr_off = reinterpret_cast<int32_t *>(w + L.csr_off);
   op->csr_inc = reinterpret_cast<int32_t *>(w + L.csr_inc);
   op->evec = reinterpret_cast<double *>(w + L.evec);
+  op->elmat = (op->fine && op->P == 2) ? reinterpret_cast<double *>(w + L.elmat) : nullptr;
+  op->elmat_prec = -1;
   if (!op->fine) {
     op->geo = reinterpret_cast<double *>(w + L.geo);
     op->state64 = reinterpret_cast<double *>(w + L.st64);
@@ -312,6 +315,7 @@ int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void 
   if (store_state) {
     op->state_ready = true;
     op->state32_ready = false;
+    op->state_version++;
   }
   return HPMG_OK;
 }
@@ -346,6 +350,19 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
     return fail(HPMG_ERR_ARG, "jacobian_apply: bad mode");
   }
   HPMG_HIP(launch_jacobian(*op, precision, mode, u, du, y, S(stream)));
+  return HPMG_OK;
+}
+
+int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream) {
+  int st = check_ready(op, "assemble_elements");
+  if (st) return st;
+  if ((st = check_prec(precision, "assemble_elements"))) return st;
+  if (!op->fine || op->P != 2 || !op->elmat)
+    return fail(HPMG_ERR_UNSUPPORTED, "assemble_elements: only for coarse operators of order 1");
+  if (!op->fine->state_ready) return fail(HPMG_ERR_ARG, "assemble_elements: no stored linearisation");
+  HPMG_HIP(launch_elmat_build(*op, precision, S(stream)));
+  op->elmat_prec = precision;
+  op->elmat_version = op->fine->state_version;
   return HPMG_OK;
 }
 

@@ -75,6 +75,10 @@ struct hpmg_op_s {
   int32_t *csr_off = nullptr;  // node -> incidences (element-local records), [N + 1]
   int32_t *csr_inc = nullptr;  // record index e * P^3 + a, sorted per node, [E * P^3]
   double *evec = nullptr;      // element output records [E][P^3][3] (FP64 or FP32)
+  double *elmat = nullptr;     // P = 2 only: element matrices [E][24 col][24 row] (FP64 or FP32)
+  int elmat_prec = -1;         // precision of the built element matrices (-1: none)
+  uint64_t elmat_version = 0;  // state version they were built from
+  uint64_t state_version = 0;  // fine operators: bumped at every stored linearisation
   unsigned *flags = nullptr;
   bool geo_ready = false, state_ready = false, state32_ready = false;
   void *host_extra = nullptr;  // host-side tables and scalars owned by the handle
@@ -112,6 +116,7 @@ hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipS
 hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
                       double *mub, double *lamb, hipStream_t s);
 hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s);
+hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s);
 bool use_atomic_scatter();
 
 // Vector kernels.
@@ -140,6 +145,11 @@ hipError_t launch_cheb_first(int prec, int64_t n, const void *dinv, const void *
                              void *r, void *d, void *x, double inv_theta, hipStream_t s);
 hipError_t launch_cheb_step(int prec, int64_t n, const void *dinv, void *r, const void *Ad, void *d,
                             void *x, double c1, double c2, hipStream_t s);
+
+hipError_t launch_pcg_update(int prec, int64_t n, double *sc, const void *p, const void *q, void *x, void *r,
+                             const void *dinv, void *z, double *partial, hipStream_t s);
+hipError_t launch_pcg_dir(int prec, int64_t n, const double *sc, const void *z, void *p, hipStream_t s);
+hipError_t launch_set_scalar(double *sc, int k, double v, hipStream_t s);
 
 size_t prec_size(int prec);
 

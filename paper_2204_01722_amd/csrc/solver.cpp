@@ -129,6 +129,39 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
 // Jacobi-PCG on level L from x = 0 with right-hand side L.b.  fixed > 0 runs exactly
 // that many iterations; otherwise stops at ||r|| <= rtol ||b||.  Records the CG
 // coefficients when asked (eigenvalue estimate).
+// Same iteration with every scalar kept on the device; the host reads the residual
+// norm only every `check` iterations (at most check - 1 extra iterations).
+int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, int check, hipStream_t s,
+               int *its_out) {
+  int st;
+  double *sc = mg->scal;
+  HPMG_HIP(launch_init_bc(prec, L.n / 3, nullptr, nullptr, L.x, s));
+  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, 0.0, L.b, L.r, s));
+  HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, sc + 2, s));  // sc[2] = rz, sc[3] = rr
+  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.z, 0.0, L.z, L.d, s));
+  HPMG_HIP(hipMemcpyAsync(sc, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));  // sc[0] = rz
+  HPMG_HIP(launch_set_scalar(sc, 5, 0.0, s));
+  if ((st = read_scalars(mg, 4, s))) return st;
+  const double bn = std::sqrt(mg->host[3]);
+  *its_out = 0;
+  if (fixed <= 0 && bn == 0.0) return HPMG_OK;
+  const int limit = fixed > 0 ? fixed : maxit;
+  int its = 0;
+  while (its < limit) {
+    if ((st = apply(mg, L, prec, L.d, L.t, s))) return st;
+    HPMG_HIP(launch_dot(prec, L.n, L.d, L.t, mg->red, sc + 1, s));
+    HPMG_HIP(launch_pcg_update(prec, L.n, sc, L.d, L.t, L.x, L.r, L.dinv, L.z, mg->red, s));
+    ++its;
+    if (fixed <= 0 && (its % check == 0 || its == limit)) {
+      if ((st = read_scalars(mg, 6, s))) return st;
+      if (mg->host[5] != 0.0 || std::sqrt(mg->host[3]) <= rtol * bn) break;
+    }
+    HPMG_HIP(launch_pcg_dir(prec, L.n, sc, L.z, L.d, s));
+  }
+  *its_out = its;
+  return HPMG_OK;
+}
+
 int pcg(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, hipStream_t s, int *its_out,
         std::vector<double> *alphas, std::vector<double> *betas) {
   int st;
@@ -195,8 +228,7 @@ int cycle(hpmg_mg_s *mg, int l, hipStream_t s) {
   Level &L = mg->lv[l];
   if (l + 1 == (int)mg->lv.size()) {
     int its = 0;
-    st = pcg(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its, s, &its, nullptr,
-             nullptr);
+    st = pcg_device(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its, 4, s, &its);
     mg->last_coarse_its = its;
     mg->n_coarse_its += its;
     return st;
@@ -246,6 +278,12 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
   for (Level &L : mg->lv) {
     HPMG_HIP(launch_diagonal(*L.op, prec, L.dinv, s));
     HPMG_HIP(launch_recip(prec, L.n, L.dinv, s));
+  }
+  Level &Lc = mg->lv.back();
+  if (mg->prm.coarse_element_matrices && Lc.op->P == 2 && Lc.op->elmat) {
+    HPMG_HIP(launch_elmat_build(*Lc.op, prec, s));
+    Lc.op->elmat_prec = prec;
+    Lc.op->elmat_version = fine->state_version;
   }
   for (size_t l = 0; l + 1 < mg->lv.size(); ++l) {
     Level &L = mg->lv[l];
@@ -335,6 +373,7 @@ void hpmg_mg_default_params(hpmg_mg_params *p) {
   p->coarse_maxit = 10000;
   p->coarse_fixed_its = 0;
   p->precision = HPMG_F64;
+  p->coarse_element_matrices = 1;
 }
 
 int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *params, hpmg_mg *out) {
@@ -465,6 +504,7 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
   for (int step = 0; step < n_steps; ++step) {
     HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0 / n_steps, lift, 1.0, u, s));
     HPMG_HIP(launch_residual(*fine, u, F, true, s));
+    fine->state_version++;
     fine->state_ready = true;
     fine->state32_ready = false;
     HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
@@ -500,6 +540,7 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
       }
       HPMG_HIP(launch_axpby(HPMG_F64, n, alpha, du, 1.0, u, s));
       HPMG_HIP(launch_residual(*fine, u, F, true, s));
+    fine->state_version++;
       fine->state32_ready = false;
       HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
       if ((st = read_scalars(mg, 1, s))) return st;

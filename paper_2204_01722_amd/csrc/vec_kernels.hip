@@ -198,6 +198,94 @@ __global__ __launch_bounds__(RED_BLOCKS) void k_final(const double *__restrict__
   }
 }
 
+// ---- device-resident Jacobi-PCG step (no host round trip per iteration) -------------
+// Scalar slots: sc[0] rz, sc[1] p.q, sc[2] rz_new, sc[3] r.r, sc[5] breakdown flag,
+// sc[6] beta.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_update(int64_t n, const double *__restrict__ sc,
+                                                   const T *__restrict__ p, const T *__restrict__ q,
+                                                   T *__restrict__ x, T *__restrict__ r,
+                                                   const T *__restrict__ dinv, T *__restrict__ z,
+                                                   double *__restrict__ partial) {
+  const double pq = sc[1];
+  const T a = (T)(pq > 0.0 ? sc[0] / pq : 0.0);
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_store<2>(v, partial);
+}
+
+__global__ __launch_bounds__(RED_BLOCKS) void k_pcg_final(const double *__restrict__ partial, int nb,
+                                                          double *__restrict__ sc) {
+  __shared__ double s[RED_BLOCKS];
+  double tot[2];
+  for (int k = 0; k < 2; ++k) {
+    s[threadIdx.x] = threadIdx.x < (unsigned)nb ? partial[k * nb + threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int w = RED_BLOCKS / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+      __syncthreads();
+    }
+    tot[k] = s[0];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double rz_old = sc[0];
+    sc[6] = rz_old != 0.0 ? tot[0] / rz_old : 0.0;
+    sc[2] = tot[0];
+    sc[3] = tot[1];
+    sc[0] = tot[0];
+    if (!(sc[1] > 0.0)) sc[5] = 1.0;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_dir(int64_t n, const double *__restrict__ sc, const T *__restrict__ z,
+                                                T *__restrict__ p) {
+  const T b = (T)sc[6];
+  GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
+}
+
+__global__ void k_set_scalar(double *__restrict__ sc, int k, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) sc[k] = v;
+}
+
+}  // namespace
+
+hipError_t launch_pcg_update(int prec, int64_t n, double *sc, const void *p, const void *q, void *x, void *r,
+                             const void *dinv, void *z, double *partial, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_pcg_update<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, (const double *)p, (const double *)q, (double *)x,
+                                                   (double *)r, (const double *)dinv, (double *)z, partial);
+  else
+    k_pcg_update<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, (const float *)p, (const float *)q, (float *)x,
+                                                  (float *)r, (const float *)dinv, (float *)z, partial);
+  k_pcg_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir(int prec, int64_t n, const double *sc, const void *z, void *p, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_pcg_dir<double><<<grid_for(n), BS, 0, s>>>(n, sc, (const double *)z, (double *)p);
+  else
+    k_pcg_dir<float><<<grid_for(n), BS, 0, s>>>(n, sc, (const float *)z, (float *)p);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_scalar(double *sc, int k, double v, hipStream_t s) {
+  k_set_scalar<<<1, 64, 0, s>>>(sc, k, v);
+  return hipGetLastError();
+}
+
+namespace {
+
 }  // namespace
 
 size_t prec_size(int prec) { return prec == HPMG_F64 ? sizeof(double) : sizeof(float); }

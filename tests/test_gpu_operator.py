@@ -149,6 +149,12 @@ def test_coarse_levels_and_transfer(n, orders, faces):
         assert rel(t2n(opc.jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
         assert rel(t2n(opc.jacobian(_dev(x).float(), "f32")), Kc @ x.reshape(-1)) < TOL32
         assert rel(t2n(opc.diagonal("f64")), Kc.diagonal()) < TOL64
+        if orders[l] == 1:
+            # order-1 coarse level from dense element matrices
+            opc.assemble_elements("f64")
+            assert rel(t2n(opc.jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
+            opc.assemble_elements("f32")
+            assert rel(t2n(opc.jacobian(_dev(x).float(), "f32")), Kc @ x.reshape(-1)) < TOL32
         # prolong_add: y += M_f P M_c x
         y0 = inputs.random_vector(opf.n_nodes, 20 + l)
         yt = _dev(y0.copy())
@@ -240,3 +246,20 @@ def test_full_size_sampled(n, p):
     assert rel(r[nodes], r_ref) < TOL64
     assert rel(y[nodes], y_ref) < TOL64
     torch.cuda.synchronize()
+
+
+def test_element_matrices_go_stale_with_the_state():
+    """Element matrices built from one linearisation are not used after the fine
+    operator stores a new one: the coarse apply follows the new state."""
+    print_case("elmat_stale")
+    faces = {"x0": (1, 1, 1)}
+    m, H = _setup(2, 2, faces=faces, orders=[2, 1])
+    u1 = inputs.config1_u(m, amplitude=0.05)
+    u2 = inputs.config1_u(m, amplitude=0.02, seed=9)
+    H.fine.residual(_dev(u1), store_state=True)
+    H.ops[1].assemble_elements("f64")
+    H.fine.residual(_dev(u2), store_state=True)
+    _, Ks = _levels_oracle(m, H, u2, faces)
+    Kc = fem.apply_bc(Ks[1], H.masks[1])
+    x = inputs.random_vector(H.ops[1].n_nodes, 41)
+    assert rel(t2n(H.ops[1].jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
