@@ -138,29 +138,41 @@ def cpu_baseline(wl, target_s=15.0):
                       f"rate = DoF x sampled fraction / time"}
 
 
-def pmg_solve(n=16, p=4, steps=5, total_disp=0.5):
+def pmg_solve(n=16, p=4, steps=5, total_disp=0.5, inclusions=False, monitor=False):
     """FP64 vs mixed-precision p-MG Newton solve (Q4 -> Q2 -> Q1, Chebyshev degree 3,
-    Jacobi-PCG coarse solve to 1e-3, FCG in FP64, Newton to 1e-8), displacement of the
-    x = 1 face by `total_disp` (first `steps` of 5 load steps), x = 0 clamped."""
+    order-1 coarse level solved by Jacobi-PCG to 1e-3, FCG in FP64 to 1e-3 per Newton
+    step, Newton to 1e-8).  Default: x = 0 clamped, x = 1 face displaced by
+    `total_disp` along x in `steps` load steps.  With `inclusions`: stiff spherical
+    inclusions (E ratio 100, 20 % of the elements, radii 2-4 elements) in a soft matrix,
+    compressed by `total_disp` (negative) along x between frictionless (roller) faces:
+    u_x = 0 on x = 0, u_x = total_disp on x = 1, u_y = 0 on y = 0, u_z = 0 on z = 0."""
     import torch
     from paper_2204_01722_amd import inputs
     from paper_2204_01722_amd.binding import PMG
     from paper_2204_01722_amd.problem import Hierarchy
     faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
     m = inputs.box_mesh(n, p, jitter=0.05, seed=2204)
+    mu_e = lam_e = None
+    desc = f"x=0 clamped, x=1 face displaced by {total_disp} along x in {steps} load steps"
+    if inclusions:
+        faces = {"x0": (1, 0, 0), "x1": (1, 0, 0), "y0": (0, 1, 0), "z0": (0, 0, 1)}
+        desc = (f"roller faces x=0, y=0, z=0, x=1 face displaced by {total_disp} along x in {steps} "
+                f"load steps")
+        mu_e, lam_e, inside = inputs.inclusion_materials(m, fraction=0.2, r_elems=(2.0, 4.0), E_in=100.0,
+                                                          E_out=1.0, nu=0.3, seed=6)
+        desc += f"; stiff inclusions (E 100:1) in {inside.mean():.1%} of the elements"
     lift = torch.from_numpy(inputs.affine_lifting(m, (total_disp, 0.0, 0.0))).cuda()
-    out = {"workload": f"Q4->Q2->Q1 on {n}^3 jittered box, {3 * m.n_nodes} DoF, x=0 clamped, x=1 face "
-                       f"displaced by {total_disp} along x in {steps} load steps; Newton rtol 1e-8, FCG rtol 1e-3, "
-                       f"Chebyshev degree 3, coarse Jacobi-PCG rtol 1e-3", "dof": 3 * m.n_nodes}
+    out = {"workload": f"Q4->Q2->Q1 on {n}^3 jittered box, {3 * m.n_nodes} DoF, {desc}; Newton rtol 1e-8, "
+                       f"FCG rtol 1e-3, Chebyshev degree 3, coarse Jacobi-PCG rtol 1e-3", "dof": 3 * m.n_nodes}
     us = {}
     for prec in ("f64", "f32"):
-        H = Hierarchy(m, [p, 2, 1], faces=faces)
+        H = Hierarchy(m, [p, 2, 1], faces=faces, mu_e=mu_e, lam_e=lam_e)
         mg = PMG(H.ops, precision=prec, cheb_degree=3, coarse_rtol=1e-3)
         u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
         seeds = H.seeds(7)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        u, st = mg.newton(u, lift, steps, seeds, rtol=1e-8, lin_rtol=1e-3)
+        u, st = mg.newton(u, lift, steps, seeds, rtol=1e-8, lin_rtol=1e-3, monitor=monitor)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         key = "fp64" if prec == "f64" else "mixed"
@@ -183,6 +195,12 @@ def main():
     ap.add_argument("--only-headline", action="store_true")
     ap.add_argument("--pmg-n", type=int, default=16, help="elements per direction of the p-MG solve")
     ap.add_argument("--pmg-only", action="store_true", help="run only the FP64-vs-mixed p-MG solve")
+    ap.add_argument("--pmg-monitor", action="store_true", help="print one line per Newton iteration")
+    ap.add_argument("--pmg-inclusions", action="store_true",
+                    help="p-MG solve of the multiscale block: stiff inclusions, compression between roller faces "
+                         "in 10 load steps")
+    ap.add_argument("--pmg-strain", type=float, default=0.15,
+                    help="compressive strain of the multiscale block (0.15: the 16^3 block stays stable)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); this build has no "
@@ -195,7 +213,12 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     if args.pmg_only:
-        print(json.dumps({"pmg_solve": pmg_solve(n=args.pmg_n)}))
+        if args.pmg_inclusions:
+            res = pmg_solve(n=args.pmg_n, steps=10, total_disp=-args.pmg_strain, inclusions=True,
+                            monitor=args.pmg_monitor)
+        else:
+            res = pmg_solve(n=args.pmg_n, monitor=args.pmg_monitor)
+        print(json.dumps({"pmg_solve": res}))
         return
 
     print("[bench] building Q4 34^3 workload", file=sys.stderr, flush=True)

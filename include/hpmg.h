@@ -233,19 +233,27 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
                    int *its, double *relres, void *stream);
 
 /* a15: Newton with load stepping and the critical-point line search (Section III-A).
- * Step k = 1..n_steps starts from u + lift / n_steps (lift holds the full imposed
- * displacement on constrained components and an extension elsewhere) and iterates
- * until ||F(u)|| <= rtol ||F(u_start)||.  Linear solves: FCG + V-cycle to lin_rtol.
- * Per-step Newton counts and total Krylov iterations are written to stats (host):
+ * Step k = 1..n_steps adds lift / n_steps to u (lift holds the full imposed displacement
+ * on constrained components and an extension elsewhere) and iterates until
+ * ||F(u)|| <= rtol ||F(u_start)||.  The first correction of a load increment uses the
+ * tangent of the previous converged state (an Euler predictor), later ones the tangent
+ * at the current iterate.  Linear solves: FCG + V-cycle to lin_rtol (a negative-
+ * curvature breakdown truncates the solve and the line search takes the direction found
+ * so far).  A step length whose point has an inverted element or a non-finite residual
+ * is halved (at most 6 times).  A load increment whose Newton solve fails (iteration
+ * limit, no admissible step, no descent direction) is retried from the previous
+ * converged state in halves, at most 6 times per load step.  Statistics (host):
  *   stats[0] = total Newton iterations, stats[1] = total FCG iterations,
- *   stats[2] = final relative residual of the last step, stats[3] = failed steps,
- *   stats[4 + k] = Newton iterations of step k (k < n_steps, at most 60 steps). */
+ *   stats[2] = final relative residual of the last increment, stats[3] = halvings,
+ *   stats[4 + k] = Newton iterations spent in load step k (k < n_steps, at most 60). */
 typedef struct {
   double rtol;      /* Newton relative residual tolerance (1e-8) */
   int max_newton;   /* per load step (20) */
   double lin_rtol;  /* FCG relative tolerance (1e-3) */
   int lin_maxit;    /* (500) */
   int line_search;  /* 1: critical-point secant step, clipped to [0.1, 1.5] */
+  int monitor;      /* (0) 1: one line per Newton iteration on stderr: load, iteration,
+                       relative residual, FCG iterations and outcome, step length */
 } hpmg_newton_params;
 void hpmg_newton_default_params(hpmg_newton_params *p);
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,

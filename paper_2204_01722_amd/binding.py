@@ -41,7 +41,7 @@ class MGParams(C.Structure):
 
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_newton", C.c_int), ("lin_rtol", C.c_double),
-                ("lin_maxit", C.c_int), ("line_search", C.c_int)]
+                ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int)]
 
 
 _VP, _I64, _D, _I = C.c_void_p, C.c_int64, C.c_double, C.c_int
@@ -397,17 +397,22 @@ class PMG:
         return x, int(its.value), float(rel.value)
 
     def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
-               line_search=True):
+               line_search=True, monitor=False):
         prm = NewtonParams()
         lib().hpmg_newton_default_params(C.byref(prm))
         prm.rtol, prm.max_newton, prm.lin_rtol = rtol, max_newton, lin_rtol
         prm.lin_maxit, prm.line_search = lin_maxit, int(bool(line_search))
+        prm.monitor = int(bool(monitor))
         stats = (C.c_double * (4 + n_steps))()
         st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()), int(n_steps),
                                      C.byref(prm), self._seed_array(seeds), C.cast(stats, C.c_void_p),
                                      _stream())
         s = list(stats)
-        res = {"newton_its": int(s[0]), "krylov_its": int(s[1]), "final_rel": s[2], "failed_steps": int(s[3]),
+        res = {"newton_its": int(s[0]), "krylov_its": int(s[1]), "final_rel": s[2], "step_halvings": int(s[3]),
                "per_step": [int(v) for v in s[4:]]}
-        _check(st)
+        if st != 0:
+            try:
+                _check(st)
+            except HpmgError as err:
+                raise HpmgError(st, f"{err} (statistics so far: {res})") from None
         return u, res

@@ -4,6 +4,7 @@
 // flow (CG coefficients, norms) through a pinned buffer.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <string>
 #include <vector>
 
@@ -35,7 +36,7 @@ struct hpmg_mg_s {
   double *host = nullptr;    // pinned host mirror (8)
   // fine FP64 vectors for the Krylov and Newton drivers
   double *fr = nullptr, *fr2 = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr;
-  double *nF = nullptr, *ndu = nullptr, *nut = nullptr;
+  double *nF = nullptr, *ndu = nullptr, *nut = nullptr, *nu0 = nullptr;
   int last_coarse_its = 0;
   int setup_done = 0;
   // counters since creation: V-cycles, coarse iterations, operator applies per level
@@ -77,6 +78,7 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   mg->nF = reinterpret_cast<double *>(take(nf));
   mg->ndu = reinterpret_cast<double *>(take(nf));
   mg->nut = reinterpret_cast<double *>(take(nf));
+  mg->nu0 = reinterpret_cast<double *>(take(nf));
   return o;
 }
 
@@ -334,6 +336,10 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
     if ((st = read_scalars(mg, 1, s))) return st;
     const double pq = mg->host[0];
     if (!(pq > 0.0) || !std::isfinite(rz)) {
+      // Negative curvature (or a non-finite preconditioned residual): stop here.  The
+      // iterate so far is returned; before the first step the preconditioned residual is
+      // returned instead, so a caller can still search along a descent direction.
+      if (its == 0 && std::isfinite(rz)) HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0, z, 1.0, x, s));
       *its_out = its;
       *rel_out = rel;
       return fail(HPMG_ERR_BREAKDOWN, "fcg: p^T A p <= 0");
@@ -485,6 +491,107 @@ void hpmg_newton_default_params(hpmg_newton_params *p) {
   p->lin_rtol = 1e-3;
   p->lin_maxit = 500;
   p->line_search = 1;
+  p->monitor = 0;
+}
+
+// Stores the linearisation at u (residual with state) and returns ||F(u)||.
+static int store_state(hpmg_op fine, hpmg_mg_s *mg, const double *u, hipStream_t s, double *fnorm) {
+  int st;
+  const int64_t n = mg->lv[0].n;
+  HPMG_HIP(launch_residual(*fine, u, mg->nF, true, s));
+  fine->state_version++;
+  fine->state_ready = true;
+  fine->state32_ready = false;
+  HPMG_HIP(launch_dot(HPMG_F64, n, mg->nF, mg->nF, mg->red, mg->scal, s));
+  if ((st = read_scalars(mg, 1, s))) return st;
+  *fnorm = std::sqrt(mg->host[0]);
+  return HPMG_OK;
+}
+
+// Newton solve at one load level (Section III-A).  On entry u holds the previous
+// converged state plus the load increment and the stored linearisation belongs to that
+// previous state: the first correction is taken with that tangent (an Euler predictor
+// for the increment), later ones with the tangent at the current iterate.  Every
+// accepted point is checked for inverted elements and non-finite values; the step is
+// halved (at most 6 times) until it passes.  Returns HPMG_OK on convergence, else an
+// error that tells the caller to cut the increment.
+static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_newton_params *prm,
+                          const double *const *seeds, void *stream, double load, int *its_out, int *lin_out,
+                          double *rel_out) {
+  int st;
+  hipStream_t s = S(stream);
+  const int64_t n = mg->lv[0].n;
+  double *F = mg->nF, *du = mg->ndu, *ut = mg->nut;
+  *its_out = 0;
+  *rel_out = 0.0;
+  HPMG_HIP(launch_residual(*fine, u, F, false, s));
+  HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
+  if ((st = read_scalars(mg, 1, s))) return st;
+  const double f0 = std::sqrt(mg->host[0]);
+  unsigned fl = 0;
+  if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
+  if (fl & HPMG_FLAG_NONPOSITIVE_J) return fail(HPMG_ERR_NONPOSITIVE_J, "newton: inverted element");
+  if ((fl & HPMG_FLAG_NONFINITE) || !std::isfinite(f0)) return fail(HPMG_ERR_NONFINITE, "newton: non-finite residual");
+  double fn = f0;
+  int its = 0;
+  while (f0 > 0.0 && !(fn <= prm->rtol * f0)) {
+    if (its >= prm->max_newton) return fail(HPMG_ERR_NOT_CONVERGED, "newton: iteration limit");
+    if ((st = do_setup(mg, seeds, s))) return st;
+    HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, F, 0.0, F, ut, s));
+    HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
+    int lits = 0;
+    double lrel = 0.0;
+    st = do_fcg(fine, mg, ut, du, prm->lin_rtol, prm->lin_maxit, &lits, &lrel, s);
+    *lin_out += lits;
+    if (st && st != HPMG_ERR_NOT_CONVERGED && st != HPMG_ERR_BREAKDOWN) return st;
+    const int lin_st = st;
+    double alpha = 1.0;
+    HPMG_HIP(launch_dot(HPMG_F64, n, F, du, mg->red, mg->scal, s));
+    if ((st = read_scalars(mg, 1, s))) return st;
+    const double g0 = mg->host[0];
+    if (!(g0 < 0.0)) return fail(HPMG_ERR_BREAKDOWN, "newton: no descent direction");
+    if (prm->line_search) {
+      // g(a) = F(u + a du)^T du; one secant step from a = 0 and a = 1.
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 1.0, du, ut, s));
+      HPMG_HIP(launch_residual(*fine, ut, mg->fq, false, s));
+      HPMG_HIP(launch_dot(HPMG_F64, n, mg->fq, du, mg->red, mg->scal, s));
+      if ((st = read_scalars(mg, 1, s))) return st;
+      const double g1 = mg->host[0];
+      unsigned fl2 = 0;
+      if ((st = hpmg_op_query_flags(fine, stream, &fl2))) return st;  // clears the trial point's flags
+      if (std::isfinite(g1) && !fl2 && g0 - g1 > 0.0) alpha = std::min(1.5, std::max(0.1, g0 / (g0 - g1)));
+      else if (!std::isfinite(g1) || fl2) alpha = 0.5;
+    }
+    // Accept u + alpha du, halving alpha while the point has an inverted element or a
+    // non-finite residual.  The state stored by the last evaluation belongs to the
+    // accepted point.
+    bool ok = false;
+    for (int bt = 0; bt < 7; ++bt) {
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, alpha, du, ut, s));
+      HPMG_HIP(launch_residual(*fine, ut, F, true, s));
+      fine->state_version++;
+      fine->state_ready = true;
+      fine->state32_ready = false;
+      HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
+      if ((st = read_scalars(mg, 1, s))) return st;
+      fn = std::sqrt(mg->host[0]);
+      unsigned fl3 = 0;
+      if ((st = hpmg_op_query_flags(fine, stream, &fl3))) return st;
+      ok = std::isfinite(fn) && !(fl3 & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE));
+      if (ok) break;
+      alpha *= 0.5;
+    }
+    if (!ok) return fail(HPMG_ERR_NONPOSITIVE_J, "newton: no admissible step length");
+    HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, ut, 0.0, ut, u, s));
+    ++its;
+    *its_out = its;
+    *rel_out = fn / f0;
+    if (prm->monitor)
+      std::fprintf(stderr, "[newton] load %.6f it %d rel %.3e fcg %d (%s, rel %.2e) alpha %.3f\n", load, its,
+                   fn / f0, lits, lin_st == HPMG_OK ? "ok" : lin_st == HPMG_ERR_BREAKDOWN ? "breakdown" : "maxit",
+                   lrel, alpha);
+  }
+  return HPMG_OK;
 }
 
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
@@ -497,66 +604,63 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
   if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "newton_solve: call qdata_setup first");
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
-  double *F = mg->nF, *du = mg->ndu, *ut = mg->nut;
   for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;
-  int total_newton = 0, total_lin = 0, failed = 0;
+  int total_newton = 0, total_lin = 0, cuts = 0;
   double final_rel = 0.0;
+  // Load increments of 1/n_steps; an increment whose Newton solve fails is retried from
+  // the previous converged state in halves (at most 6 halvings per step).
+  bool state_at_u = false;  // does the stored linearisation belong to u?
   for (int step = 0; step < n_steps; ++step) {
-    HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0 / n_steps, lift, 1.0, u, s));
-    HPMG_HIP(launch_residual(*fine, u, F, true, s));
-    fine->state_version++;
-    fine->state_ready = true;
-    fine->state32_ready = false;
-    HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 1, s))) return st;
-    const double f0 = std::sqrt(mg->host[0]);
-    double fn = f0;
-    int its = 0;
-    while (its < prm->max_newton && fn > prm->rtol * f0 && f0 > 0.0) {
-      unsigned fl = 0;
-      if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
-      if (fl & HPMG_FLAG_NONPOSITIVE_J) return fail(HPMG_ERR_NONPOSITIVE_J, "newton_solve: inverted element");
-      if (fl & HPMG_FLAG_NONFINITE) return fail(HPMG_ERR_NONFINITE, "newton_solve: non-finite residual");
-      if ((st = do_setup(mg, seeds, s))) return st;
-      HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, F, 0.0, F, ut, s));
-      HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
-      int lits = 0;
-      double lrel = 0.0;
-      st = do_fcg(fine, mg, ut, du, prm->lin_rtol, prm->lin_maxit, &lits, &lrel, s);
-      total_lin += lits;
-      if (st && st != HPMG_ERR_NOT_CONVERGED) return st;
-      double alpha = 1.0;
-      if (prm->line_search) {
-        // g(a) = F(u + a du)^T du; one secant step from a = 0 and a = 1.
-        HPMG_HIP(launch_dot(HPMG_F64, n, F, du, mg->red, mg->scal, s));
-        if ((st = read_scalars(mg, 1, s))) return st;
-        const double g0 = mg->host[0];
-        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 1.0, du, ut, s));
-        HPMG_HIP(launch_residual(*fine, ut, mg->fq, false, s));
-        HPMG_HIP(launch_dot(HPMG_F64, n, mg->fq, du, mg->red, mg->scal, s));
-        if ((st = read_scalars(mg, 1, s))) return st;
-        const double g1 = mg->host[0];
-        if (g0 - g1 > 0.0) alpha = std::min(1.5, std::max(0.1, g0 / (g0 - g1)));
+    double done = 0.0, dt = 1.0;
+    int halvings = 0;
+    while (done < 1.0 - 1e-12) {
+      const double inc = std::min(dt, 1.0 - done);
+      if (!state_at_u) {
+        double f_prev = 0.0;
+        if ((st = store_state(fine, mg, u, s, &f_prev))) return st;
+        unsigned fl = 0;
+        if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
+        if (fl & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE) || !std::isfinite(f_prev))
+          return fail(HPMG_ERR_NONPOSITIVE_J, "newton_solve: the starting state has an inverted element");
+        state_at_u = true;
       }
-      HPMG_HIP(launch_axpby(HPMG_F64, n, alpha, du, 1.0, u, s));
-      HPMG_HIP(launch_residual(*fine, u, F, true, s));
-    fine->state_version++;
-      fine->state32_ready = false;
-      HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
-      if ((st = read_scalars(mg, 1, s))) return st;
-      fn = std::sqrt(mg->host[0]);
-      ++its;
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 0.0, u, mg->nu0, s));
+      HPMG_HIP(launch_axpby(HPMG_F64, n, inc / n_steps, lift, 1.0, u, s));
+      int its = 0;
+      double rel = 0.0;
+      st = newton_at_load(fine, mg, u, prm, seeds, stream, (step + done + inc) / n_steps, &its, &total_lin, &rel);
+      if (st && prm->monitor)
+        std::fprintf(stderr, "[newton] load %.6f failed (%s); halving the increment\n", (step + done + inc) / n_steps,
+                     hpmg_last_error());
+      total_newton += its;
+      stats[4 + step] += its;
+      if (st == HPMG_OK) {
+        state_at_u = its > 0;  // with no iteration the stored state is still the previous one
+        done += inc;
+        final_rel = rel;
+        dt = std::min(1.0, 2.0 * inc);
+        continue;
+      }
+      if (st != HPMG_ERR_NOT_CONVERGED && st != HPMG_ERR_NONPOSITIVE_J && st != HPMG_ERR_NONFINITE &&
+          st != HPMG_ERR_BREAKDOWN)
+        return st;
+      ++cuts;
+      if (++halvings > 6) {
+        stats[0] = total_newton;
+        stats[1] = total_lin;
+        stats[2] = final_rel;
+        stats[3] = cuts;
+        return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: load step failed after 6 halvings");
+      }
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, u, s));
+      state_at_u = false;
+      dt = 0.5 * inc;
     }
-    final_rel = f0 > 0.0 ? fn / f0 : 0.0;
-    if (fn > prm->rtol * f0) ++failed;
-    total_newton += its;
-    stats[4 + step] = its;
   }
   stats[0] = total_newton;
   stats[1] = total_lin;
   stats[2] = final_rel;
-  stats[3] = failed;
-  if (failed) return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: a load step did not converge");
+  stats[3] = cuts;
   return HPMG_OK;
 }
 

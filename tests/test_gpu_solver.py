@@ -114,7 +114,7 @@ def test_newton_uniaxial_closed_form(prec):
     lt = _uniaxial_stretch(lx, MU, LAM)
     exact = m.coords * np.array([lx - 1.0, lt - 1.0, lt - 1.0])
     assert np.abs(t2n(u) - exact).max() < 1e-9
-    assert st["failed_steps"] == 0
+    assert st["step_halvings"] == 0
     print(f"[newton] precision={prec} stats={st}", flush=True)
 
 
