@@ -85,21 +85,34 @@ __device__ __forceinline__ void interp_t(T *b, T *a, const T *sB, int q, bool li
 
 // Reference gradient at quadrature point q from quadrature values (collocated
 // derivative): G[c][k] = d(component c)/d xi_k.
+//
+// The empty asm statements pin each component's sums before the next component's LDS
+// reads are issued.  Without them the scheduler hoists all 3 x 15 reads ahead of the
+// first FMA, which costs ~50 extra VGPRs in FP64 and one wave per SIMD of occupancy.
 template <typename T, int Q, int NC>
 __device__ __forceinline__ void grad_q(const T *in, const T *sD, int q, T (&G)[NC][3]) {
   constexpr int Q3 = Q * Q * Q;
   const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
-#pragma unroll
-  for (int c = 0; c < NC; ++c) G[c][0] = G[c][1] = G[c][2] = 0;
+  T d1[Q], d2[Q], d3[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const T d1 = sD[q1 * Q + j], d2 = sD[q2 * Q + j], d3 = sD[q3 * Q + j];
+    d1[j] = sD[q1 * Q + j];
+    d2[j] = sD[q2 * Q + j];
+    d3[j] = sD[q3 * Q + j];
+  }
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      G[c][0] += d1 * in[c * Q3 + j + Q * (q2 + Q * q3)];
-      G[c][1] += d2 * in[c * Q3 + q1 + Q * (j + Q * q3)];
-      G[c][2] += d3 * in[c * Q3 + q1 + Q * (q2 + Q * j)];
+  for (int c = 0; c < NC; ++c) {
+    T g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      g0 += d1[j] * in[c * Q3 + j + Q * (q2 + Q * q3)];
+      g1 += d2[j] * in[c * Q3 + q1 + Q * (j + Q * q3)];
+      g2 += d3[j] * in[c * Q3 + q1 + Q * (q2 + Q * j)];
     }
+    asm volatile("" : "+v"(g0), "+v"(g1), "+v"(g2)::"memory");
+    G[c][0] = g0;
+    G[c][1] = g1;
+    G[c][2] = g2;
   }
 }
 
@@ -110,19 +123,25 @@ __device__ __forceinline__ void grad_t_q(const T *f, const T *sD, int q, T *out,
   constexpr int Q3 = Q * Q * Q;
   if (!live || q >= Q3) return;
   const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
-  T acc[3] = {0, 0, 0};
+  T d1[Q], d2[Q], d3[Q];
 #pragma unroll
   for (int j = 0; j < Q; ++j) {
-    const T d1 = sD[j * Q + q1], d2 = sD[j * Q + q2], d3 = sD[j * Q + q3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      acc[c] += d1 * f[(c * 3 + 0) * Q3 + j + Q * (q2 + Q * q3)];
-      acc[c] += d2 * f[(c * 3 + 1) * Q3 + q1 + Q * (j + Q * q3)];
-      acc[c] += d3 * f[(c * 3 + 2) * Q3 + q1 + Q * (q2 + Q * j)];
-    }
+    d1[j] = sD[j * Q + q1];
+    d2[j] = sD[j * Q + q2];
+    d3[j] = sD[j * Q + q3];
   }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) out[c * Q3 + q] = acc[c];
+  for (int c = 0; c < 3; ++c) {
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      acc += d1[j] * f[(c * 3 + 0) * Q3 + j + Q * (q2 + Q * q3)];
+      acc += d2[j] * f[(c * 3 + 1) * Q3 + q1 + Q * (j + Q * q3)];
+      acc += d3[j] * f[(c * 3 + 2) * Q3 + q1 + Q * (q2 + Q * j)];
+    }
+    asm volatile("" : "+v"(acc)::"memory");
+    out[c * Q3 + q] = acc;
+  }
 }
 
 template <typename T>
@@ -491,6 +510,208 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
   }
 }
 
+
+// ------------------------------------------------------------------------------------
+// a5 (P = Q): the same Jacobian action with register-blocked 1D contractions.
+//
+// In the kernel above every thread owns one point and each 1D contraction costs it N
+// LDS reads per output.  Here every contraction stage is run by "line tasks": a task
+// owns one line of N points along the contraction direction (for one component),
+// reads the line once, forms all N outputs in registers from the 1D table (the same
+// for every lane, so it is read through the scalar cache, not LDS) and writes them
+// back in place.  That is one LDS read and one write per point and stage instead of
+// N + 1.  The pointwise work (state loads, quadrature function, gather, records) keeps
+// the one-thread-per-point mapping and the tile layout of the other kernels.
+// ------------------------------------------------------------------------------------
+
+// Offset of point (i1, i2, i3) along a line: the line of task r (0 <= r < N^2) in
+// direction DIR starts at line_base and steps by line_step.
+template <int N, int DIR>
+__device__ __forceinline__ int line_base(int r) {
+  const int r1 = r % N, r2 = r / N;
+  return DIR == 0 ? N * (r1 + N * r2) : DIR == 1 ? r1 + N * N * r2 : r1 + N * r2;
+}
+template <int N, int DIR>
+__device__ __forceinline__ constexpr int line_step() {
+  return DIR == 0 ? 1 : DIR == 1 ? N : N * N;
+}
+
+// y = M x (TR = false, M is [N][N] row-major, row = output) or y = M^T x (TR = true).
+template <typename T, int N, bool TR>
+__device__ __forceinline__ void line_apply(const T *__restrict__ M, const T (&x)[N], T (&y)[N]) {
+#pragma unroll
+  for (int o = 0; o < N; ++o) {
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc += M[TR ? i * N + o : o * N + i] * x[i];
+    y[o] = acc;
+  }
+}
+
+// One in-place contraction stage along DIR of NC arrays [c][N^3] per element, for the
+// ET elements of a tile (element el's arrays start at buf + el * ELS, array c at
+// + c * CS).  Task t = (el, c, line).
+template <typename T, int N, int DIR, bool TR, int NC, int ET, int ELS, int CS>
+__device__ __forceinline__ void line_stage(T *buf, const T *__restrict__ M, int tid, int nt, int nel) {
+  constexpr int N2 = N * N, TASKS = NC * N2;
+  for (int t = tid; t < ET * TASKS; t += nt) {
+    const int el = t / TASKS, r = t % TASKS, c = r / N2;
+    if (el >= nel) break;
+    T *p = buf + el * ELS + c * CS + line_base<N, DIR>(r % N2);
+    T x[N], y[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = p[i * line_step<N, DIR>()];
+    line_apply<T, N, TR>(M, x, y);
+#pragma unroll
+    for (int i = 0; i < N; ++i) p[i * line_step<N, DIR>()] = y[i];
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(QT<N>::NT) void k_jacobian_lines(
+    const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
+    const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
+    const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
+  constexpr int N2 = N * N, N3 = N2 * N, ET = QT<N>::ET, NQ = QT<N>::NQ, NT = QT<N>::NT;
+  // Per element: v [3][N^3] (du, then its values at the points, then the assembled
+  // nodal result) and G [3][3][N^3] (gradient, then the flux).
+  constexpr int ELS = 12 * N3;
+  __shared__ T lds[ET * ELS];
+  const int tq = threadIdx.x, el = tq / N3, q = tq % N3;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
+  const int nel = (int)((E - tile * ET) < ET ? (E - tile * ET) : ET);
+  const bool live = tq < NQ && e < E;
+  const T *tB = tab + TAB_B, *tD = tab + TAB_D;
+  uint32_t w = 0;
+  if (live) w = emap[e * N3 + q];
+  T *v = lds + (live ? el : 0) * ELS, *G = v + 3 * N3;
+  T sv[NSTATE];
+  if (live) gather_node(du, w, true, v, q, N3);
+  if (live) {
+    const T *s = state + tile * NSTATE * NQ + tq;
+#pragma unroll
+    for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+  }
+  __syncthreads();
+  // Interpolation to the points, one direction at a time, in place.
+  line_stage<T, N, 0, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  __syncthreads();
+  line_stage<T, N, 1, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  __syncthreads();
+  line_stage<T, N, 2, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  __syncthreads();
+  // Collocated derivative in the three directions: G[c][k] = D_k v[c].
+  {
+    constexpr int TASKS = 9 * N2;
+    for (int t = tq; t < ET * TASKS; t += NT) {
+      const int te = t / TASKS, r = t % TASKS, ck = r / N2, c = ck / 3, k = ck % 3, ln = r % N2;
+      if (te >= nel) break;
+      const T *src = lds + te * ELS + c * N3;
+      T *dst = lds + te * ELS + (3 + ck) * N3;
+      T x[N], y[N];
+      if (k == 0) {
+        const int b0 = line_base<N, 0>(ln);
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = src[b0 + i];
+        line_apply<T, N, false>(tD, x, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[b0 + i] = y[i];
+      } else if (k == 1) {
+        const int b1 = line_base<N, 1>(ln);
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = src[b1 + i * N];
+        line_apply<T, N, false>(tD, x, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[b1 + i * N] = y[i];
+      } else {
+        const int b2 = line_base<N, 2>(ln);
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = src[b2 + i * N2];
+        line_apply<T, N, false>(tD, x, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) dst[b2 + i * N2] = y[i];
+      }
+    }
+  }
+  __syncthreads();
+  // Quadrature function, one thread per point, flux written over the gradient.
+  if (live) {
+    T Gq[3][3], A[3][3], tau[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) Gq[c][k] = G[(c * 3 + k) * N3 + q];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
+#pragma unroll
+    for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
+    const T c = sv[15], W = sv[16];
+    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+    T f[3][3];
+    jacobian_qf(Gq, A, tau, c, W, mu, lam, f);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) G[(i * 3 + k) * N3 + q] = f[i][k];
+  }
+  __syncthreads();
+  // Transposed derivative, x and y directions in place on the flux arrays.
+  {
+    constexpr int TASKS = 6 * N2;
+    for (int t = tq; t < ET * TASKS; t += NT) {
+      const int te = t / TASKS, r = t % TASKS, ck = r / N2, c = ck / 2, k = ck % 2, ln = r % N2;
+      if (te >= nel) break;
+      T *p = lds + te * ELS + (3 + c * 3 + k) * N3;
+      T x[N], y[N];
+      if (k == 0) {
+        const int b0 = line_base<N, 0>(ln);
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = p[b0 + i];
+        line_apply<T, N, true>(tD, x, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[b0 + i] = y[i];
+      } else {
+        const int b1 = line_base<N, 1>(ln);
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = p[b1 + i * N];
+        line_apply<T, N, true>(tD, x, y);
+#pragma unroll
+        for (int i = 0; i < N; ++i) p[b1 + i * N] = y[i];
+      }
+    }
+  }
+  __syncthreads();
+  // z direction: h = D_z^T f_z + (x and y parts), then the first transposed
+  // interpolation stage (B_z^T) in registers; the result goes to v.
+  {
+    constexpr int TASKS = 3 * N2;
+    for (int t = tq; t < ET * TASKS; t += NT) {
+      const int te = t / TASKS, r = t % TASKS, c = r / N2, ln = r % N2;
+      if (te >= nel) break;
+      const int b2 = line_base<N, 2>(ln);
+      T *f = lds + te * ELS + (3 + c * 3) * N3 + b2;
+      T x[N], y[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = f[2 * N3 + i * N2];
+      line_apply<T, N, true>(tD, x, y);
+#pragma unroll
+      for (int i = 0; i < N; ++i) y[i] += f[i * N2] + f[N3 + i * N2];
+      line_apply<T, N, true>(tB, y, x);
+      T *o = lds + te * ELS + c * N3 + b2;
+#pragma unroll
+      for (int i = 0; i < N; ++i) o[i * N2] = x[i];
+    }
+  }
+  __syncthreads();
+  line_stage<T, N, 1, true, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  __syncthreads();
+  line_stage<T, N, 0, true, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  __syncthreads();
+  if (live) store_record(ev, e, v, q, N3);
+}
 
 // ------------------------------------------------------------------------------------
 // a5': Jacobian action recomputing the linearisation from u and the geometry.
@@ -1168,6 +1389,17 @@ bool use_atomic_scatter() {
   return v == 1;
 }
 
+// Element kernels for P = Q: register-blocked line contractions unless
+// HPMG_ELEMENT_KERNEL=point selects the one-thread-per-point kernels.
+bool use_line_kernels() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("HPMG_ELEMENT_KERNEL");
+    v = (e && std::string(e) == "point") ? 0 : 1;
+  }
+  return v == 1;
+}
+
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
   const bool atom = use_atomic_scatter();
   if (atom) {
@@ -1194,6 +1426,13 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
                               T *y, T *ev, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
+  if constexpr (P == Q) {
+    if (mode == HPMG_STORED && ev && use_line_kernels()) {
+      k_jacobian_lines<T, P><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
+                                                                       f.mu_e, f.lam_e, ev, op.E);
+      return hipGetLastError();
+    }
+  }
   if (mode == HPMG_STORED) {
     k_jacobian_stored<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
                                                                         f.mu_e, f.lam_e, y, ev, op.E);
