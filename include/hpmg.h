@@ -103,7 +103,8 @@ void hpmg_op_destroy(hpmg_op op);
 int hpmg_op_set_material(hpmg_op op, double mu, double lambda, const double *mu_e,
                          const double *lambda_e);
 /* Device workspace needed by the operator (tables, geometric factors, stored
- * linearisation in FP64 and FP32, multiplicities, reduction scratch, flags). */
+ * linearisation in FP64 and FP32, element records and node incidence lists for the
+ * assembly, reduction scratch, flags). */
 int hpmg_op_workspace_bytes(hpmg_op op, size_t *bytes);
 /* Binds a caller-owned device buffer of at least the queried size (256-byte aligned)
  * and uploads the reference tables; enqueued on `stream`. */
@@ -139,9 +140,9 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
                         void *y, void *stream);
 /* Order-1 coarse operators only (Pc = 2): builds the dense 24 x 24 element matrices
  * of this level's Galerkin operator from the fine operator's stored linearisation
- * (the element-level triple product B^T D B of Section III-D), in
- * `precision`.  While the fine linearisation is unchanged, stored-mode applies of this
- * operator in that precision then read the element matrices (576 scalars per element)
+ * (the element-level triple product B^T D B of Section III-D), in `precision`.  While
+ * the fine linearisation is unchanged, stored-mode applies of this operator in that
+ * precision then read the element matrices (symmetric: 300 scalars per element)
  * instead of the fine-quadrature linearisation.  A new stored linearisation makes them
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
@@ -154,9 +155,13 @@ int hpmg_state_cast_f32(hpmg_op op, void *stream);
 int hpmg_diagonal(hpmg_op op, int precision, void *diag, void *stream);
 
 /* a11: p-transfer between a coarse operator and its fine operator (eq. mg_prolong):
- *   hpmg_prolong_add: yf += M_f P xc   (P = sum_e E_f^T diag(1/m_f) B_ctof E_c)
+ *   hpmg_prolong_add: yf += M_f P xc   (P = sum_e E_f^T O_e B_ctof E_c)
  *   hpmg_restrict:    rc  = M_c P^T rf (restriction is the transpose, Section III-B)
- * Vectors in `precision` (double or float). */
+ * O_e selects the fine nodes owned by element e (each node has exactly one owner, its
+ * first element), which equals the paper's averaging diag(1/m_f) over the m_f elements
+ * sharing a node because every element interpolates the same continuous coarse field
+ * there.  M masks constrained components.  Deterministic (no atomics).  Vectors in
+ * `precision` (double or float). */
 int hpmg_prolong_add(hpmg_op coarse, hpmg_op fine, int precision, const void *xc, void *yf,
                      void *stream);
 int hpmg_restrict(hpmg_op fine, hpmg_op coarse, int precision, const void *rf, void *rc,

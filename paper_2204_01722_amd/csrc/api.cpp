@@ -61,7 +61,7 @@ int fill_tables(hpmg_op_s *op, OpExtra *x) {
 
 // Byte offsets of the workspace parts; the last entry is the total.
 struct Layout {
-  size_t flags, tab64, tab32, emap, inv64, inv32, scratch, csr_off, csr_inc, evec, elmat, geo, st64, st32, total;
+  size_t flags, tab64, tab32, emap, scratch, csr_off, csr_inc, evec, elmat, geo, st64, st32, total;
 };
 
 Layout layout_of(const hpmg_op_s *op) {
@@ -71,14 +71,12 @@ Layout layout_of(const hpmg_op_s *op) {
   L.tab64 = o; o += align256(TAB_SIZE * sizeof(double));
   L.tab32 = o; o += align256(TAB_SIZE * sizeof(float));
   L.emap = o; o += align256((size_t)op->E * op->P * op->P * op->P * sizeof(uint32_t));
-  L.inv64 = o; o += align256((size_t)op->N * sizeof(double));
-  L.inv32 = o; o += align256((size_t)op->N * sizeof(float));
   L.scratch = o; o += align256(((size_t)op->E + 2 * RED_BLOCKS + 64) * sizeof(double));
   const size_t nrec = (size_t)op->E * op->P * op->P * op->P;
   L.csr_off = o; o += align256(((size_t)op->N + 1) * sizeof(int32_t));
   L.csr_inc = o; o += align256(nrec * sizeof(int32_t));
   L.evec = o; o += align256(nrec * 3 * sizeof(double));
-  L.elmat = o; o += (op->fine && op->P == 2) ? align256((size_t)op->E * 576 * sizeof(double)) : 0;
+  L.elmat = o; o += (op->fine && op->P == 2) ? align256((size_t)op->E * 300 * sizeof(double)) : 0;
   const size_t nq = (size_t)op->tiles * op->NQ;
   if (!op->fine) {
     L.geo = o; o += align256(nq * NGEO * sizeof(double));
@@ -209,8 +207,6 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   op->tab64 = reinterpret_cast<double *>(w + L.tab64);
   op->tab32 = reinterpret_cast<float *>(w + L.tab32);
   op->emap = reinterpret_cast<uint32_t *>(w + L.emap);
-  op->invmult64 = reinterpret_cast<double *>(w + L.inv64);
-  op->invmult32 = reinterpret_cast<float *>(w + L.inv32);
   op->scratch = reinterpret_cast<double *>(w + L.scratch);
   op->csr_off = reinterpret_cast<int32_t *>(w + L.csr_off);
   op->csr_inc = reinterpret_cast<int32_t *>(w + L.csr_inc);
@@ -229,7 +225,6 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   HPMG_HIP(hipMemcpyAsync(op->tab64, x->t64.data(), TAB_SIZE * sizeof(double), hipMemcpyHostToDevice, s));
   HPMG_HIP(hipMemcpyAsync(op->tab32, x->t32.data(), TAB_SIZE * sizeof(float), hipMemcpyHostToDevice, s));
   HPMG_HIP(launch_build_emap(*op, s));
-  HPMG_HIP(launch_multiplicity(*op, s));
   // The host sources of the asynchronous copies live in the handle; make sure the
   // copies have been consumed before returning so the caller may reuse the stream freely.
   HPMG_HIP(hipStreamSynchronize(s));
@@ -255,6 +250,8 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   for (int64_t k = 0; k < nrec; ++k) inc[cur[en[k]]++] = (int32_t)k;
   HPMG_HIP(hipMemcpy(op->csr_off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HPMG_HIP(hipMemcpy(op->csr_inc, inc.data(), inc.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HPMG_HIP(launch_mark_owners(*op, s));
+  HPMG_HIP(hipStreamSynchronize(s));
   return HPMG_OK;
 }
 

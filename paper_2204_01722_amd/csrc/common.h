@@ -44,6 +44,9 @@ __host__ __device__ constexpr int tab_ctof(int Pf) { return TAB_CTOF + (Pf - 2) 
 // flags of the node's three components in bits 28..30.
 constexpr uint32_t EMAP_ID_MASK = (1u << 28) - 1u;
 constexpr int EMAP_BC_SHIFT = 28;
+// Set on exactly one record of every node (its first record in element order): the
+// element that writes the node in the p-transfers.
+constexpr uint32_t EMAP_OWNER = 1u << 31;
 constexpr int64_t MAX_NODES = int64_t(1) << 28;
 
 constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
@@ -69,13 +72,11 @@ struct hpmg_op_s {
   double *geo = nullptr;       // fine only
   double *state64 = nullptr;   // fine only
   float *state32 = nullptr;    // fine only
-  double *invmult64 = nullptr; // 1 / (number of elements sharing the node)
-  float *invmult32 = nullptr;
   double *scratch = nullptr;   // reductions
   int32_t *csr_off = nullptr;  // node -> incidences (element-local records), [N + 1]
   int32_t *csr_inc = nullptr;  // record index e * P^3 + a, sorted per node, [E * P^3]
   double *evec = nullptr;      // element output records [E][P^3][3] (FP64 or FP32)
-  double *elmat = nullptr;     // P = 2 only: element matrices [E][24 col][24 row] (FP64 or FP32)
+  double *elmat = nullptr;     // P = 2 only: element matrices [E][300], upper triangle row-major (FP64 or FP32)
   int elmat_prec = -1;         // precision of the built element matrices (-1: none)
   uint64_t elmat_version = 0;  // state version they were built from
   uint64_t state_version = 0;  // fine operators: bumped at every stored linearisation
@@ -102,7 +103,7 @@ int ctof_table(int Pf, int Pc, double *M);
 // Launchers (op_kernels.hip / vec_kernels.hip).  All return hipError_t of the launch.
 bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
-hipError_t launch_multiplicity(const hpmg_op_s &op, hipStream_t s);
+hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_qdata(const hpmg_op_s &op, const double *coords, hipStream_t s);
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s);
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,

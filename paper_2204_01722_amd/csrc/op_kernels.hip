@@ -512,82 +512,91 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
 
 
 // ------------------------------------------------------------------------------------
-// a5 (P = Q): the same Jacobian action with register-blocked 1D contractions.
+// a5: the same Jacobian action with register-blocked 1D contractions.
 //
-// In the kernel above every thread owns one point and each 1D contraction costs it N
-// LDS reads per output.  Here every contraction stage is run by "line tasks": a task
-// owns one line of N points along the contraction direction (for one component),
-// reads the line once, forms all N outputs in registers from the 1D table (the same
-// for every lane, so it is read through the scalar cache, not LDS) and writes them
-// back in place.  That is one LDS read and one write per point and stage instead of
-// N + 1.  The pointwise work (state loads, quadrature function, gather, records) keeps
-// the one-thread-per-point mapping and the tile layout of the other kernels.
+// In the kernel above every thread owns one point and each 1D contraction costs it one
+// LDS read per input of every output.  Here every contraction stage is run by "line
+// tasks": a task owns one line of points along the contraction direction (for one
+// component), reads the line once, forms all of its outputs in registers from the 1D
+// table (the same for every lane, so it is read through the scalar cache, not LDS) and
+// writes them back in place.  That is one LDS read and one write per point and stage.
+// Nodal (P^3) and quadrature (Q^3) arrays share one Q^3 frame per component, indexed
+// i1 + Q i2 + Q^2 i3, so the interpolation stages can work in place.  The pointwise
+// work (state loads, quadrature function, gather, records) keeps the one-thread-per-
+// point mapping and the tile layout of the other kernels.
 // ------------------------------------------------------------------------------------
 
-// Offset of point (i1, i2, i3) along a line: the line of task r (0 <= r < N^2) in
-// direction DIR starts at line_base and steps by line_step.
-template <int N, int DIR>
+// First frame offset and stride of line r of a stage along DIR whose lines run over
+// the other two directions with extents L1 (the faster one) and L2.
+template <int Q, int DIR, int L1>
 __device__ __forceinline__ int line_base(int r) {
-  const int r1 = r % N, r2 = r / N;
-  return DIR == 0 ? N * (r1 + N * r2) : DIR == 1 ? r1 + N * N * r2 : r1 + N * r2;
+  const int r1 = r % L1, r2 = r / L1;
+  return DIR == 0 ? Q * (r1 + Q * r2) : DIR == 1 ? r1 + Q * Q * r2 : r1 + Q * r2;
 }
-template <int N, int DIR>
+template <int Q, int DIR>
 __device__ __forceinline__ constexpr int line_step() {
-  return DIR == 0 ? 1 : DIR == 1 ? N : N * N;
+  return DIR == 0 ? 1 : DIR == 1 ? Q : Q * Q;
 }
 
-// y = M x (TR = false, M is [N][N] row-major, row = output) or y = M^T x (TR = true).
-template <typename T, int N, bool TR>
-__device__ __forceinline__ void line_apply(const T *__restrict__ M, const T (&x)[N], T (&y)[N]) {
+// y = M x with M [NO][NI] row-major (TR = false) or y = M^T x with M [NI][NO] (TR = true).
+template <typename T, int NI, int NO, bool TR>
+__device__ __forceinline__ void line_apply(const T *__restrict__ M, const T (&x)[NI], T (&y)[NO]) {
 #pragma unroll
-  for (int o = 0; o < N; ++o) {
+  for (int o = 0; o < NO; ++o) {
     T acc = 0;
 #pragma unroll
-    for (int i = 0; i < N; ++i) acc += M[TR ? i * N + o : o * N + i] * x[i];
+    for (int i = 0; i < NI; ++i) acc += M[TR ? i * NO + o : o * NI + i] * x[i];
     y[o] = acc;
   }
 }
 
-// One in-place contraction stage along DIR of NC arrays [c][N^3] per element, for the
-// ET elements of a tile (element el's arrays start at buf + el * ELS, array c at
-// + c * CS).  Task t = (el, c, line).
-template <typename T, int N, int DIR, bool TR, int NC, int ET, int ELS, int CS>
+// One in-place contraction stage along DIR (NI inputs -> NO outputs per line) of the
+// three component frames of each of the tile's elements (element el at buf + el * ELS,
+// component c at + c * Q^3).  Lines run over extents L1 x L2 of the other directions.
+template <typename T, int Q, int DIR, int NI, int NO, bool TR, int L1, int L2, int ET, int ELS>
 __device__ __forceinline__ void line_stage(T *buf, const T *__restrict__ M, int tid, int nt, int nel) {
-  constexpr int N2 = N * N, TASKS = NC * N2;
+  constexpr int NL = L1 * L2, TASKS = 3 * NL, Q3 = Q * Q * Q, ST = line_step<Q, DIR>();
   for (int t = tid; t < ET * TASKS; t += nt) {
-    const int el = t / TASKS, r = t % TASKS, c = r / N2;
+    const int el = t / TASKS, r = t % TASKS, c = r / NL;
     if (el >= nel) break;
-    T *p = buf + el * ELS + c * CS + line_base<N, DIR>(r % N2);
-    T x[N], y[N];
+    T *p = buf + el * ELS + c * Q3 + line_base<Q, DIR, L1>(r % NL);
+    T x[NI], y[NO];
 #pragma unroll
-    for (int i = 0; i < N; ++i) x[i] = p[i * line_step<N, DIR>()];
-    line_apply<T, N, TR>(M, x, y);
+    for (int i = 0; i < NI; ++i) x[i] = p[i * ST];
+    line_apply<T, NI, NO, TR>(M, x, y);
 #pragma unroll
-    for (int i = 0; i < N; ++i) p[i * line_step<N, DIR>()] = y[i];
+    for (int i = 0; i < NO; ++i) p[i * ST] = y[i];
   }
 }
 
-template <typename T, int N>
-__global__ __launch_bounds__(QT<N>::NT) void k_jacobian_lines(
+template <typename T, int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
     const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
-  constexpr int N2 = N * N, N3 = N2 * N, ET = QT<N>::ET, NQ = QT<N>::NQ, NT = QT<N>::NT;
-  // Per element: v [3][N^3] (du, then its values at the points, then the assembled
-  // nodal result) and G [3][3][N^3] (gradient, then the flux).
-  constexpr int ELS = 12 * N3;
+  constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
+  // Per element: v [3][Q^3] (du, then its values at the points, then the nodal result)
+  // and G [3][3][Q^3] (gradient, then the flux).
+  constexpr int ELS = 12 * Q3;
   __shared__ T lds[ET * ELS];
-  const int tq = threadIdx.x, el = tq / N3, q = tq % N3;
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
   const int64_t tile = xcd_tile();
   const int64_t e = tile * ET + el;
   const int nel = (int)((E - tile * ET) < ET ? (E - tile * ET) : ET);
   const bool live = tq < NQ && e < E;
   const T *tB = tab + TAB_B, *tD = tab + TAB_D;
-  uint32_t w = 0;
-  if (live) w = emap[e * N3 + q];
-  T *v = lds + (live ? el : 0) * ELS, *G = v + 3 * N3;
+  T *v = lds + (live ? el : 0) * ELS, *G = v + 3 * Q3;
+  // Frame index of node q (q < P^3).
+  const int qn = (q % P) + Q * ((q / P) % P) + Q2 * (q / (P * P));
+  if (live && q < P3) {
+    const uint32_t w = emap[e * P3 + q];
+    const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
+    const T x0 = src[0], x1 = src[1], x2 = src[2];
+    v[qn] = ((w >> EMAP_BC_SHIFT) & 1u) ? T(0) : x0;
+    v[Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 1)) & 1u) ? T(0) : x1;
+    v[2 * Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : x2;
+  }
   T sv[NSTATE];
-  if (live) gather_node(du, w, true, v, q, N3);
   if (live) {
     const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
@@ -595,42 +604,42 @@ __global__ __launch_bounds__(QT<N>::NT) void k_jacobian_lines(
   }
   __syncthreads();
   // Interpolation to the points, one direction at a time, in place.
-  line_stage<T, N, 0, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  line_stage<T, Q, 0, P, Q, false, P, P, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  line_stage<T, N, 1, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  line_stage<T, Q, 1, P, Q, false, Q, P, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  line_stage<T, N, 2, false, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  line_stage<T, Q, 2, P, Q, false, Q, Q, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
   // Collocated derivative in the three directions: G[c][k] = D_k v[c].
   {
-    constexpr int TASKS = 9 * N2;
+    constexpr int TASKS = 9 * Q2;
     for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, ck = r / N2, c = ck / 3, k = ck % 3, ln = r % N2;
+      const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 3, k = ck % 3, ln = r % Q2;
       if (te >= nel) break;
-      const T *src = lds + te * ELS + c * N3;
-      T *dst = lds + te * ELS + (3 + ck) * N3;
-      T x[N], y[N];
+      const T *src = lds + te * ELS + c * Q3;
+      T *dst = lds + te * ELS + (3 + ck) * Q3;
+      T x[Q], y[Q];
       if (k == 0) {
-        const int b0 = line_base<N, 0>(ln);
+        const int b0 = line_base<Q, 0, Q>(ln);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = src[b0 + i];
-        line_apply<T, N, false>(tD, x, y);
+        for (int i = 0; i < Q; ++i) x[i] = src[b0 + i];
+        line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < N; ++i) dst[b0 + i] = y[i];
+        for (int i = 0; i < Q; ++i) dst[b0 + i] = y[i];
       } else if (k == 1) {
-        const int b1 = line_base<N, 1>(ln);
+        const int b1 = line_base<Q, 1, Q>(ln);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = src[b1 + i * N];
-        line_apply<T, N, false>(tD, x, y);
+        for (int i = 0; i < Q; ++i) x[i] = src[b1 + i * Q];
+        line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < N; ++i) dst[b1 + i * N] = y[i];
+        for (int i = 0; i < Q; ++i) dst[b1 + i * Q] = y[i];
       } else {
-        const int b2 = line_base<N, 2>(ln);
+        const int b2 = line_base<Q, 2, Q>(ln);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = src[b2 + i * N2];
-        line_apply<T, N, false>(tD, x, y);
+        for (int i = 0; i < Q; ++i) x[i] = src[b2 + i * Q2];
+        line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < N; ++i) dst[b2 + i * N2] = y[i];
+        for (int i = 0; i < Q; ++i) dst[b2 + i * Q2] = y[i];
       }
     }
   }
@@ -641,7 +650,7 @@ __global__ __launch_bounds__(QT<N>::NT) void k_jacobian_lines(
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) Gq[c][k] = G[(c * 3 + k) * N3 + q];
+      for (int k = 0; k < 3; ++k) Gq[c][k] = G[(c * 3 + k) * Q3 + q];
 #pragma unroll
     for (int k = 0; k < 3; ++k)
 #pragma unroll
@@ -655,62 +664,68 @@ __global__ __launch_bounds__(QT<N>::NT) void k_jacobian_lines(
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int k = 0; k < 3; ++k) G[(i * 3 + k) * N3 + q] = f[i][k];
+      for (int k = 0; k < 3; ++k) G[(i * 3 + k) * Q3 + q] = f[i][k];
   }
   __syncthreads();
   // Transposed derivative, x and y directions in place on the flux arrays.
   {
-    constexpr int TASKS = 6 * N2;
+    constexpr int TASKS = 6 * Q2;
     for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, ck = r / N2, c = ck / 2, k = ck % 2, ln = r % N2;
+      const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 2, k = ck % 2, ln = r % Q2;
       if (te >= nel) break;
-      T *p = lds + te * ELS + (3 + c * 3 + k) * N3;
-      T x[N], y[N];
+      T *p = lds + te * ELS + (3 + c * 3 + k) * Q3;
+      T x[Q], y[Q];
       if (k == 0) {
-        const int b0 = line_base<N, 0>(ln);
+        const int b0 = line_base<Q, 0, Q>(ln);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = p[b0 + i];
-        line_apply<T, N, true>(tD, x, y);
+        for (int i = 0; i < Q; ++i) x[i] = p[b0 + i];
+        line_apply<T, Q, Q, true>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < N; ++i) p[b0 + i] = y[i];
+        for (int i = 0; i < Q; ++i) p[b0 + i] = y[i];
       } else {
-        const int b1 = line_base<N, 1>(ln);
+        const int b1 = line_base<Q, 1, Q>(ln);
 #pragma unroll
-        for (int i = 0; i < N; ++i) x[i] = p[b1 + i * N];
-        line_apply<T, N, true>(tD, x, y);
+        for (int i = 0; i < Q; ++i) x[i] = p[b1 + i * Q];
+        line_apply<T, Q, Q, true>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < N; ++i) p[b1 + i * N] = y[i];
+        for (int i = 0; i < Q; ++i) p[b1 + i * Q] = y[i];
       }
     }
   }
   __syncthreads();
   // z direction: h = D_z^T f_z + (x and y parts), then the first transposed
-  // interpolation stage (B_z^T) in registers; the result goes to v.
+  // interpolation stage (B_z^T, Q -> P) in registers; the result goes to v.
   {
-    constexpr int TASKS = 3 * N2;
+    constexpr int TASKS = 3 * Q2;
     for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, c = r / N2, ln = r % N2;
+      const int te = t / TASKS, r = t % TASKS, c = r / Q2, ln = r % Q2;
       if (te >= nel) break;
-      const int b2 = line_base<N, 2>(ln);
-      T *f = lds + te * ELS + (3 + c * 3) * N3 + b2;
-      T x[N], y[N];
+      const int b2 = line_base<Q, 2, Q>(ln);
+      const T *f = lds + te * ELS + (3 + c * 3) * Q3 + b2;
+      T x[Q], y[Q], z[P];
 #pragma unroll
-      for (int i = 0; i < N; ++i) x[i] = f[2 * N3 + i * N2];
-      line_apply<T, N, true>(tD, x, y);
+      for (int i = 0; i < Q; ++i) x[i] = f[2 * Q3 + i * Q2];
+      line_apply<T, Q, Q, true>(tD, x, y);
 #pragma unroll
-      for (int i = 0; i < N; ++i) y[i] += f[i * N2] + f[N3 + i * N2];
-      line_apply<T, N, true>(tB, y, x);
-      T *o = lds + te * ELS + c * N3 + b2;
+      for (int i = 0; i < Q; ++i) y[i] += f[i * Q2] + f[Q3 + i * Q2];
+      line_apply<T, Q, P, true>(tB, y, z);
+      T *o = lds + te * ELS + c * Q3 + b2;
 #pragma unroll
-      for (int i = 0; i < N; ++i) o[i * N2] = x[i];
+      for (int i = 0; i < P; ++i) o[i * Q2] = z[i];
     }
   }
   __syncthreads();
-  line_stage<T, N, 1, true, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  line_stage<T, Q, 1, Q, P, true, Q, P, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  line_stage<T, N, 0, true, 3, ET, ELS, N3>(lds, tB, tq, NT, nel);
+  line_stage<T, Q, 0, Q, P, true, P, P, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  if (live) store_record(ev, e, v, q, N3);
+  if (live && q < P3) {
+    T *o = ev + ((int64_t)e * P3 + q) * 3;
+    const T y0 = v[qn], y1 = v[Q3 + qn], y2 = v[2 * Q3 + qn];
+    o[0] = y0;
+    o[1] = y1;
+    o[2] = y2;
+  }
 }
 
 // ------------------------------------------------------------------------------------
@@ -796,7 +811,7 @@ template <typename T, int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
     const uint32_t *__restrict__ emap, const T *__restrict__ state, const T *__restrict__ tab,
     double mu0, double lam0, const double *__restrict__ mu_e, const double *__restrict__ lam_e,
-    T *__restrict__ diag, int64_t E) {
+    T *__restrict__ ev, int64_t E) {
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 3 * Q3, S1 = 3 * Q3;
   __shared__ T sBB[Q * P], sBG[Q * P], sGG[Q * P];
@@ -861,11 +876,9 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
     }
   }
   if (live && q < P3) {
-    const uint32_t w = emap[e * P3 + q];
-    const uint32_t node = w & EMAP_ID_MASK;
+    T *p = ev + ((int64_t)e * P3 + q) * 3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      if (!((w >> (EMAP_BC_SHIFT + c)) & 1u)) atomic_add(&diag[(int64_t)node * 3 + c], acc[c]);
+    for (int c = 0; c < 3; ++c) p[c] = acc[c];
   }
 }
 
@@ -879,6 +892,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
 // fine-quadrature linearisation at Q = 5).
 // ------------------------------------------------------------------------------------
 constexpr int ELB = 8;  // elements per workgroup (8 x 24 = 192 threads)
+constexpr int ELMAT_PACKED = 300;  // 24 x 25 / 2 entries of the symmetric element matrix
+__device__ __forceinline__ constexpr int elmat_index(int r, int j) { return r * (47 - r) / 2 + j; }
 
 template <typename TO, int Q>
 __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restrict__ state,
@@ -947,20 +962,29 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restri
       for (int i = 0; i < 3; ++i) acc[a * 3 + i] += d0 * f[i][0] + d1 * f[i][1] + d2 * f[i][2];
     }
   }
-  TO *out = K + ((int64_t)e * 24 + j) * 24;
+  // The matrix is symmetric: store its upper triangle, row-major (entry (r, j), r <= j,
+  // at r (47 - r) / 2 + j); column j supplies rows r <= j.
+  TO *out = K + (int64_t)e * ELMAT_PACKED;
 #pragma unroll
-  for (int r = 0; r < 24; ++r) out[r] = (TO)acc[r];
+  for (int r = 0; r < 24; ++r)
+    if (r <= j) out[elmat_index(r, j)] = (TO)acc[r];
 }
 
-// y_e = K_e x_e for order-1 elements (records for the node-centric assembly).
+// y_e = K_e x_e for order-1 elements (records for the node-centric assembly).  The
+// workgroup's packed matrices (8 x 300 contiguous values) are staged through LDS with
+// coalesced loads; thread r then forms row r from the triangle.
 template <typename T>
 __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__restrict__ emap,
                                                           const T *__restrict__ K, const T *__restrict__ x,
                                                           T *__restrict__ ev, int64_t E) {
   __shared__ T sx[ELB * 24];
+  __shared__ T sK[ELB * ELMAT_PACKED];
   const int t = threadIdx.x, el = t / 24, r = t % 24;
-  const int64_t e = (int64_t)blockIdx.x * ELB + el;
+  const int64_t e0 = (int64_t)blockIdx.x * ELB, e = e0 + el;
   const bool live = e < E;
+  const int64_t nel = (E - e0) < ELB ? (E - e0) : ELB;
+  const T *Kb = K + e0 * ELMAT_PACKED;
+  for (int i = t; i < nel * ELMAT_PACKED; i += ELB * 24) sK[i] = Kb[i];
   if (live) {
     const uint32_t w = emap[e * 8 + r / 3];
     const int c = r % 3;
@@ -968,12 +992,12 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__rest
   }
   __syncthreads();
   if (!live) return;
-  const T *Ke = K + (int64_t)e * 576 + r;
+  const T *Ke = sK + el * ELMAT_PACKED;
   const T *xe = sx + el * 24;
   T acc = 0;
 #pragma unroll
-  for (int jj = 0; jj < 24; ++jj) acc += Ke[jj * 24] * xe[jj];
-  ev[(int64_t)e * 24 + r] = acc;
+  for (int jj = 0; jj < 24; ++jj) acc += Ke[jj < r ? elmat_index(jj, r) : elmat_index(r, jj)] * xe[jj];
+  ev[e * 24 + r] = acc;
 }
 
 // ------------------------------------------------------------------------------------
@@ -982,7 +1006,7 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__rest
 template <typename T, int PF, int PC>
 __global__ __launch_bounds__(QT<PF>::NT) void k_prolong_add(
     const uint32_t *__restrict__ emap_c, const uint32_t *__restrict__ emap_f, const T *__restrict__ xc,
-    const T *__restrict__ invm, const T *__restrict__ tab_c, T *__restrict__ yf, int64_t E) {
+    const T *__restrict__ tab_c, T *__restrict__ yf, int64_t E) {
   constexpr int F3 = PF * PF * PF, C3 = PC * PC * PC, ET = QT<PF>::ET, NQ = ET * F3, NT = QT<PF>::NT;
   constexpr int S = 3 * F3;
   __shared__ T sM[PF * PC];
@@ -1003,19 +1027,21 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_prolong_add(
   __syncthreads();
   stage<T, PF, PF, PC, 2, PF, false, 3>(a, b, sM, q, live);
   __syncthreads();
-  if (live) {
-    const T s = invm[wf & EMAP_ID_MASK];
-    b[q] *= s;
-    b[F3 + q] *= s;
-    b[2 * F3 + q] *= s;
-    scatter_node(yf, wf, true, b, q, F3);
+  // Every element sharing a fine node interpolates the same value there (the coarse
+  // field is continuous); the node's owner element adds it.  No atomics, and the
+  // result does not depend on the order in which workgroups run.
+  if (live && (wf & EMAP_OWNER)) {
+    T *p = yf + (int64_t)(wf & EMAP_ID_MASK) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (!((wf >> (EMAP_BC_SHIFT + c)) & 1u)) p[c] += b[c * F3 + q];
   }
 }
 
 template <typename T, int PF, int PC>
 __global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
-    const uint32_t *__restrict__ emap_f, const uint32_t *__restrict__ emap_c, const T *__restrict__ rf,
-    const T *__restrict__ invm, const T *__restrict__ tab_c, T *__restrict__ rc, int64_t E) {
+    const uint32_t *__restrict__ emap_f, const T *__restrict__ rf, const T *__restrict__ tab_c,
+    T *__restrict__ ev_c, int64_t E) {
   constexpr int F3 = PF * PF * PF, C3 = PC * PC * PC, ET = QT<PF>::ET, NQ = ET * F3, NT = QT<PF>::NT;
   constexpr int S = 3 * F3;
   __shared__ T sM[PF * PC];
@@ -1026,13 +1052,15 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
   const bool live = tq < NQ && e < E;
   load_tables(sM, tab_c, tab_ctof(PF), PF * PC, tq, NT);
   T *a = lds + (live ? el : 0) * S, *b = lds + ET * S + (live ? el : 0) * S;
+  // Transpose of the owner-written prolongation: each fine node's value enters
+  // through its owner element only.
   if (live) {
     const uint32_t w = emap_f[e * F3 + q];
-    const T s = invm[w & EMAP_ID_MASK];
-    gather_node(rf, w, true, a, q, F3);
-    a[q] *= s;
-    a[F3 + q] *= s;
-    a[2 * F3 + q] *= s;
+    if (w & EMAP_OWNER) {
+      gather_node(rf, w, true, a, q, F3);
+    } else {
+      a[q] = a[F3 + q] = a[2 * F3 + q] = T(0);
+    }
   }
   __syncthreads();
   stage<T, PF, PF, PF, 2, PC, true, 3>(a, b, sM, q, live);
@@ -1041,7 +1069,7 @@ __global__ __launch_bounds__(QT<PF>::NT) void k_restrict(
   __syncthreads();
   stage<T, PF, PC, PC, 0, PC, true, 3>(a, b, sM, q, live);
   __syncthreads();
-  if (live && q < C3) scatter_node(rc, emap_c[e * C3 + q], true, b, q, C3);
+  if (live && q < C3) store_record(ev_c, e, b, q, C3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1272,19 +1300,6 @@ __global__ void k_build_emap(const int32_t *__restrict__ en, const uint8_t *__re
   emap[i] = w;
 }
 
-__global__ void k_count(const uint32_t *__restrict__ emap, double *__restrict__ cnt, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomic_add(&cnt[emap[i] & EMAP_ID_MASK], 1.0);
-}
-
-__global__ void k_invert_count(double *__restrict__ c64, float *__restrict__ c32, int64_t N) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double v = c64[i] > 0.0 ? 1.0 / c64[i] : 0.0;
-  c64[i] = v;
-  c32[i] = (float)v;
-}
-
 __global__ void k_zero_d(double *__restrict__ x, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) x[i] = 0.0;
@@ -1296,7 +1311,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ inc, const T *__restrict__ ev,
                                                   const uint8_t *__restrict__ mask, const T *__restrict__ src,
-                                                  T *__restrict__ y) {
+                                                  T fill, T *__restrict__ y) {
   for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
     const int32_t k0 = off[n], k1 = off[n + 1];
     T a0 = 0, a1 = 0, a2 = 0;
@@ -1308,9 +1323,9 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__re
     }
     if (mask) {
       const uint8_t *m = mask + n * 3;
-      if (m[0]) a0 = src ? src[n * 3] : T(0);
-      if (m[1]) a1 = src ? src[n * 3 + 1] : T(0);
-      if (m[2]) a2 = src ? src[n * 3 + 2] : T(0);
+      if (m[0]) a0 = src ? src[n * 3] : fill;
+      if (m[1]) a1 = src ? src[n * 3 + 1] : fill;
+      if (m[2]) a2 = src ? src[n * 3 + 2] : fill;
     }
     T *o = y + n * 3;
     o[0] = a0;
@@ -1321,12 +1336,21 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__re
 
 inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// y = assembled element records of `op`; constrained components take src (or `fill`).
 template <typename T>
-hipError_t assemble(const hpmg_op_s &op, const T *src, T *y, hipStream_t s) {
+hipError_t assemble(const hpmg_op_s &op, const T *src, T *y, hipStream_t s, T fill = T(0)) {
   int64_t g = (op.N + 255) / 256;
   if (g < 1) g = 1;
-  k_assemble<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src, y);
+  k_assemble<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src, fill,
+                                             y);
   return hipGetLastError();
+}
+
+// The first record of every node (incidence lists are in record order) owns it.
+__global__ void k_mark_owners(int64_t N, const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
+                              uint32_t *__restrict__ emap) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n < N && off[n] < off[n + 1]) emap[inc[off[n]]] |= EMAP_OWNER;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1359,11 +1383,8 @@ hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_multiplicity(const hpmg_op_s &op, hipStream_t s) {
-  const int64_t n = op.E * op.P * op.P * op.P;
-  k_zero_d<<<grid1d(op.N, 256), 256, 0, s>>>(op.invmult64, op.N);
-  k_count<<<grid1d(n, 256), 256, 0, s>>>(op.emap, op.invmult64, n);
-  k_invert_count<<<grid1d(op.N, 256), 256, 0, s>>>(op.invmult64, op.invmult32, op.N);
+hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s) {
+  k_mark_owners<<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, op.emap);
   return hipGetLastError();
 }
 
@@ -1389,8 +1410,8 @@ bool use_atomic_scatter() {
   return v == 1;
 }
 
-// Element kernels for P = Q: register-blocked line contractions unless
-// HPMG_ELEMENT_KERNEL=point selects the one-thread-per-point kernels.
+// Stored-linearisation Jacobian: register-blocked line contractions unless
+// HPMG_ELEMENT_KERNEL=point selects the one-thread-per-point kernel.
 bool use_line_kernels() {
   static int v = -1;
   if (v < 0) {
@@ -1426,12 +1447,10 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
                               T *y, T *ev, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
-  if constexpr (P == Q) {
-    if (mode == HPMG_STORED && ev && use_line_kernels()) {
-      k_jacobian_lines<T, P><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
-                                                                       f.mu_e, f.lam_e, ev, op.E);
-      return hipGetLastError();
-    }
+  if (mode == HPMG_STORED && ev && use_line_kernels()) {
+    k_jacobian_lines<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
+                                                                        f.mu_e, f.lam_e, ev, op.E);
+    return hipGetLastError();
   }
   if (mode == HPMG_STORED) {
     k_jacobian_stored<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
@@ -1477,14 +1496,13 @@ hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double
 
 hipError_t launch_diagonal(const hpmg_op_s &op, int prec, void *diag, hipStream_t s) {
   const hpmg_op_s &f = op.fine ? *op.fine : op;
-  hipError_t e = launch_fill_bc_one(prec, op.N, op.mask, diag, s);
-  if (e != hipSuccess) return e;
   if (prec == HPMG_F64) {
 #define X(p, q)                                                                                    \
   if (op.P == p && op.Q == q) {                                                                    \
     k_diagonal<double, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                              \
-        op.emap, f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, (double *)diag, op.E);     \
-    return hipGetLastError();                                                                      \
+        op.emap, f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, (double *)op.evec, op.E);    \
+    hipError_t e = hipGetLastError();                                                              \
+    return e != hipSuccess ? e : assemble<double>(op, nullptr, (double *)diag, s, 1.0);            \
   }
     HPMG_PQ_LIST(X)
 #undef X
@@ -1492,8 +1510,9 @@ hipError_t launch_diagonal(const hpmg_op_s &op, int prec, void *diag, hipStream_
 #define X(p, q)                                                                                   \
   if (op.P == p && op.Q == q) {                                                                   \
     k_diagonal<float, p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(                              \
-        op.emap, f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e, (float *)diag, op.E);     \
-    return hipGetLastError();                                                                     \
+        op.emap, f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e, (float *)op.evec, op.E);     \
+    hipError_t e = hipGetLastError();                                                             \
+    return e != hipSuccess ? e : assemble<float>(op, nullptr, (float *)diag, s, 1.0f);            \
   }
     HPMG_PQ_LIST(X)
 #undef X
@@ -1508,10 +1527,10 @@ hipError_t launch_prolong_add(const hpmg_op_s &c, const hpmg_op_s &f, int prec, 
   if (f.P == pf && c.P == pc) {                                                                       \
     if (prec == HPMG_F64)                                                                             \
       k_prolong_add<double, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(c.emap, f.emap, (const double *)xc,    \
-                                                                f.invmult64, c.tab64, (double *)yf, f.E); \
+                                                                c.tab64, (double *)yf, f.E);          \
     else                                                                                              \
       k_prolong_add<float, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(c.emap, f.emap, (const float *)xc,      \
-                                                               f.invmult32, c.tab32, (float *)yf, f.E); \
+                                                               c.tab32, (float *)yf, f.E);            \
     return hipGetLastError();                                                                         \
   }
   HPMG_PP_LIST(X)
@@ -1522,18 +1541,19 @@ hipError_t launch_prolong_add(const hpmg_op_s &c, const hpmg_op_s &f, int prec, 
 
 hipError_t launch_restrict(const hpmg_op_s &f, const hpmg_op_s &c, int prec, const void *rf, void *rc,
                            hipStream_t s) {
-  hipError_t e = launch_init_bc(prec, c.N, nullptr, nullptr, rc, s);
-  if (e != hipSuccess) return e;
   const unsigned grid = grid1d(f.E, elems_per_tile(f.P));
 #define X(pf, pc)                                                                                    \
   if (f.P == pf && c.P == pc) {                                                                      \
-    if (prec == HPMG_F64)                                                                            \
-      k_restrict<double, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, c.emap, (const double *)rf,      \
-                                                             f.invmult64, c.tab64, (double *)rc, f.E); \
-    else                                                                                             \
-      k_restrict<float, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, c.emap, (const float *)rf,        \
-                                                            f.invmult32, c.tab32, (float *)rc, f.E);  \
-    return hipGetLastError();                                                                        \
+    if (prec == HPMG_F64) {                                                                          \
+      k_restrict<double, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, (const double *)rf, c.tab64,     \
+                                                             (double *)c.evec, f.E);                 \
+      hipError_t e = hipGetLastError();                                                              \
+      return e != hipSuccess ? e : assemble<double>(c, nullptr, (double *)rc, s);                    \
+    }                                                                                                \
+    k_restrict<float, pf, pc><<<grid, QT<pf>::NT, 0, s>>>(f.emap, (const float *)rf, c.tab32,         \
+                                                          (float *)c.evec, f.E);                      \
+    hipError_t e = hipGetLastError();                                                                \
+    return e != hipSuccess ? e : assemble<float>(c, nullptr, (float *)rc, s);                        \
   }
   HPMG_PP_LIST(X)
 #undef X

@@ -68,7 +68,7 @@ def test_host_argument_validation(L):
     assert L.hpmg_op_create(3, 3, 10, 100, fake, None, C.byref(h)) == 0
     nb = C.c_size_t()
     assert L.hpmg_op_workspace_bytes(h, C.byref(nb)) == 0
-    # workspace: tables + map + multiplicities + scratch + 10 + 17 + 17/2 doubles per point
+    # workspace: tables + map + records + incidence + scratch + 10 + 17 + 17/2 doubles per point
     assert nb.value > 10 * 27 * (10 + 17) * 8
     assert L.hpmg_residual(h, fake, fake, 1, None) == 4  # workspace not bound
     assert b"workspace" in L.hpmg_last_error()
