@@ -39,7 +39,7 @@ def measured_traffic():
     """HBM bytes per apply from the committed counter summary, if it was taken on the
     current kernel source (else None)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_jacobian_stored_q4_fp64_34cubed.json")
+    path = os.path.join(ROOT, "profiles", "traffic_jacobian_q4_fp64_34cubed.json")
     src = os.path.join(ROOT, "paper_2204_01722_amd", "csrc", "op_kernels.hip")
     if not os.path.exists(path):
         return None
@@ -193,7 +193,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--only-headline", action="store_true")
-    ap.add_argument("--pmg-n", type=int, default=16, help="elements per direction of the p-MG solve")
+    ap.add_argument("--pmg-n", type=int, default=40, help="elements per direction of the p-MG solve")
     ap.add_argument("--pmg-only", action="store_true", help="run only the FP64-vs-mixed p-MG solve")
     ap.add_argument("--pmg-monitor", action="store_true", help="print one line per Newton iteration")
     ap.add_argument("--pmg-inclusions", action="store_true",
@@ -291,7 +291,7 @@ def main():
         "config": {"workload": "Q4 (P=5 GLL nodes, 5^3 Gauss points) on a 34^3 jittered unit box, "
                                "7,714,059 DoF, stored 17-scalar FP64 Jacobian apply, max stretch 1.3, "
                                "E=1, nu=0.3", "global_batch": 1, "seq_len": 0, "parallelism": "none"},
-        "roofline": {"bound": "hbm", "kernel": "k_jacobian_stored<double,5,5> + k_assemble<double> (one apply)",
+        "roofline": {"bound": "hbm", "kernel": "k_jacobian_lines<double,5,5> + k_assemble<double> (one apply)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": measured_traffic(),
                      "algorithmic_bytes_per_launch": nbytes},

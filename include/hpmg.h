@@ -247,7 +247,8 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
  * so far).  A step length whose point has an inverted element or a non-finite residual
  * is halved (at most 6 times).  A load increment whose Newton solve fails (iteration
  * limit, no admissible step, no descent direction) is retried from the previous
- * converged state in halves, at most 6 times per load step.  Statistics (host):
+ * converged state in halves, at most 6 times in a row; after a converged increment the
+ * increment doubles again up to the full step.  Statistics (host):
  *   stats[0] = total Newton iterations, stats[1] = total FCG iterations,
  *   stats[2] = final relative residual of the last increment, stats[3] = halvings,
  *   stats[4 + k] = Newton iterations spent in load step k (k < n_steps, at most 60). */

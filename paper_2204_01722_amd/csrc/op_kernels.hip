@@ -1140,7 +1140,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
     const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ w,
     const double *__restrict__ geo, const double *__restrict__ state, const double *__restrict__ tab,
     double mu0, double lam0, const double *__restrict__ mu_e, const double *__restrict__ lam_e,
-    double *__restrict__ ub, double *__restrict__ mub, double *__restrict__ lamb, int64_t E) {
+    double *__restrict__ ev, double *__restrict__ mub, double *__restrict__ lamb, int64_t E) {
   using T = double;
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int NC = STORED ? 3 : 6;
@@ -1259,11 +1259,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
   }
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    const uint32_t node = emap[e * P3 + q] & EMAP_ID_MASK;
-#pragma unroll
-    for (int c2 = 0; c2 < 3; ++c2) atomic_add(&ub[(int64_t)node * 3 + c2], a[c2 * P3 + q]);
-  }
+  if (live && q < P3) store_record(ev, e, a, q, P3);
 }
 
 // Geometric factors out of the tiled layout into [E][10][Q^3].
@@ -1312,7 +1308,10 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__re
                                                   const int32_t *__restrict__ inc, const T *__restrict__ ev,
                                                   const uint8_t *__restrict__ mask, const T *__restrict__ src,
                                                   T fill, T *__restrict__ y) {
-  for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < N; n += (int64_t)gridDim.x * blockDim.x) {
+  // One node per thread; consecutive node ranges stay on one XCD (see xcd_tile), so
+  // the records of neighbouring nodes, which share elements, meet in the same L2.
+  const int64_t n = xcd_tile() * blockDim.x + threadIdx.x;
+  if (n < N) {
     const int32_t k0 = off[n], k1 = off[n + 1];
     T a0 = 0, a1 = 0, a2 = 0;
     for (int32_t k = k0; k < k1; ++k) {
@@ -1576,18 +1575,22 @@ hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipS
 
 hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
                       double *mub, double *lamb, hipStream_t s) {
-  hipError_t e = launch_init_bc(HPMG_F64, op.N, nullptr, nullptr, ub, s);
-  if (e != hipSuccess) return e;
+  double *ev = op.evec;
 #define X(p, q)                                                                                      \
   if (op.P == p && op.Q == q) {                                                                      \
     if (mode == HPMG_STORED)                                                                         \
       k_vjp<p, q, true><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,   \
                                                                  op.tab64, op.mu, op.lam, op.mu_e,   \
-                                                                 op.lam_e, ub, mub, lamb, op.E);     \
+                                                                 op.lam_e, ev, mub, lamb, op.E);     \
     else                                                                                             \
       k_vjp<p, q, false><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,  \
                                                                   op.tab64, op.mu, op.lam, op.mu_e,  \
-                                                                  op.lam_e, ub, mub, lamb, op.E);    \
+                                                                  op.lam_e, ev, mub, lamb, op.E);    \
+    hipError_t e = hipGetLastError();                                                                \
+    if (e != hipSuccess) return e;                                                                   \
+    /* unmasked assembly: constrained columns of u_bar are kept */                                   \
+    k_assemble<double><<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, ev, nullptr,   \
+                                                         nullptr, 0.0, ub);                          \
     return hipGetLastError();                                                                        \
   }
   HPMG_PQ_LIST(X)

@@ -608,7 +608,8 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
   int total_newton = 0, total_lin = 0, cuts = 0;
   double final_rel = 0.0;
   // Load increments of 1/n_steps; an increment whose Newton solve fails is retried from
-  // the previous converged state in halves (at most 6 halvings per step).
+  // the previous converged state in halves (at most 6 halvings in a row); after a
+  // success the increment doubles again, up to the full step.
   bool state_at_u = false;  // does the stored linearisation belong to u?
   for (int step = 0; step < n_steps; ++step) {
     double done = 0.0, dt = 1.0;
@@ -639,6 +640,7 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
         done += inc;
         final_rel = rel;
         dt = std::min(1.0, 2.0 * inc);
+        halvings = 0;
         continue;
       }
       if (st != HPMG_ERR_NOT_CONVERGED && st != HPMG_ERR_NONPOSITIVE_J && st != HPMG_ERR_NONFINITE &&
@@ -650,7 +652,7 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
         stats[1] = total_lin;
         stats[2] = final_rel;
         stats[3] = cuts;
-        return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: load step failed after 6 halvings");
+        return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: load increment failed after 6 halvings in a row");
       }
       HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, u, s));
       state_at_u = false;

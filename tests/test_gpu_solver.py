@@ -221,3 +221,50 @@ def test_adjoint_full_size_sampled():
         an = float(torch.sum(mub * dm) + torch.sum(lamb * dl))
         assert abs(fd - an) <= 1e-6 * abs(an), (k, fd, an)
     op.set_material(0.0, 0.0, mut, lamt)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_vcycle_bitwise_reproducible(prec):
+    """Every assembly in the V-cycle (operator applies, diagonals, transfers, coarse
+    element matrices, dot products) is summed in a fixed order: two setups and V-cycles
+    on the same input give bitwise identical results, however the workgroups run."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG
+    print_case("vcycle_reproducible", prec=prec)
+    m, H, u = _build(6, [4, 2, 1], {"x0": (1, 1, 1)})
+    fr = 1.0 - H.masks[0].reshape(-1)
+    r = _dev((inputs.random_vector(m.n_nodes, 23).reshape(-1) * fr).reshape(-1, 3))
+    outs = []
+    for _ in range(2):
+        pmg = PMG(H.ops, precision=prec, coarse_fixed_its=8)
+        pmg.setup(H.seeds(7))
+        outs.append(pmg.vcycle(r).clone())
+        y = H.fine.jacobian(r, precision="f64")
+        outs.append(y.clone())
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[2])
+    assert torch.equal(outs[1], outs[3])
+
+
+def test_newton_cuts_the_load_increment():
+    """50 % compression between clamped faces in one load step with at most 4 Newton
+    iterations per increment: the full increment cannot converge, so the driver halves
+    it; the result must still be the equilibrium the oracle reaches in 12 load steps
+    (Q2, 3^3 elements)."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("newton_cut")
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(3, 2, jitter=0.1)
+    H = Hierarchy(m, [2, 1], faces=faces)
+    lift_np = inputs.affine_lifting(m, (-0.5, 0.0, 0.0))
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    ref, _ = omg.newton_load_steps(d, MU, LAM, H.masks[0], lift_np, 12,
+                                   lambda K, b: spla.spsolve(K.tocsc(), b), rtol=1e-11, max_newton=30)
+    pmg = PMG(H.ops, precision="f64")
+    u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    u, st = pmg.newton(u, _dev(lift_np), 1, H.seeds(7), rtol=1e-10, max_newton=4, lin_rtol=1e-8)
+    print(f"[newton_cut] stats={st}", flush=True)
+    assert st["step_halvings"] >= 1
+    assert rel(t2n(u), ref) < 1e-7
