@@ -1,5 +1,6 @@
 """Oracle: p-multigrid transfer, Chebyshev/Jacobi smoothing, eigenvalue estimate,
-V-cycle, Jacobi-PCG, flexible CG, and the Newton load-stepping driver.
+V-cycle, Jacobi-PCG, flexible CG, the Newton load-stepping driver, and limited-memory
+BFGS with the V-cycle as initial inverse Hessian.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -22,7 +23,11 @@ Readings taken where the paper is silent:
 * the outer solver is flexible CG with the Polak-Ribiere form of beta;
 * Newton stops on the 2-norm of the residual relative to the load step's first one;
   the line search takes one secant step for ``F(u + a du)^T du = 0`` from ``a = 0, 1``
-  and clips ``a`` to ``[0.1, 1.5]`` (``a = 1`` if the secant slope is not positive).
+  and clips ``a`` to ``[0.1, 1.5]`` (``a = 1`` if the secant slope is not positive);
+* L-BFGS (Section III-A: the V-cycle as "initial inverse Hessian", same critical-point
+  line search) uses the textbook two-loop recursion over the last ``memory`` pairs
+  ``s = u_new - u``, ``y = F(u_new) - F(u)``, skips pairs with ``y^T s <= 0``, and
+  builds the V-cycle once per load step, at the lifted starting point.
 """
 from __future__ import annotations
 
@@ -259,5 +264,83 @@ def newton_load_steps(disc, mu, lam, mask, lift, n_steps, linear_solve, rtol=1e-
             u = u + a * du
             F = resid(u)
             its += 1
+        history.append(its)
+    return u, history
+
+
+def line_search_cp_dir(grad, u, d, clip=(0.1, 1.5)):
+    """Critical-point step length along a direction ``d``: one secant step on
+    ``phi(a) = grad(u + a d)^T d`` between ``a = 0`` and ``a = 1`` (Section III-A).
+    ``clip=None`` returns the unclipped secant root (exact for a quadratic energy)."""
+    g0 = grad(u) @ d
+    g1 = grad(u + d) @ d
+    if g0 - g1 <= 0.0:
+        return 1.0
+    a = g0 / (g0 - g1)
+    return a if clip is None else float(np.clip(a, clip[0], clip[1]))
+
+
+def lbfgs(grad, u0, h0, memory=5, rtol=1e-8, max_its=500, clip=(0.1, 1.5)):
+    """Limited-memory BFGS for ``grad(u) = 0`` with initial inverse Hessian ``h0``
+    (a function of a vector).  Search direction by the two-loop recursion: with
+    ``rho_i = 1 / (y_i^T s_i)``, first ``a_i = rho_i s_i^T q; q -= a_i y_i`` from the
+    newest pair to the oldest, then ``r = h0(q)``, then ``b = rho_i y_i^T r;
+    r += (a_i - b) s_i`` from the oldest to the newest; ``d = -r``.  Stops when
+    ``||grad(u)||_2 <= rtol ||grad(u0)||_2``.  Returns ``u, its, final_rel``."""
+    u = np.array(u0, dtype=np.float64, copy=True)
+    g = grad(u)
+    gn0 = np.linalg.norm(g)
+    pairs = []
+    its, rel = 0, 0.0 if gn0 == 0.0 else 1.0
+    while gn0 > 0.0 and rel > rtol and its < max_its:
+        q = g.copy()
+        alph = []
+        for s_i, y_i, rho in reversed(pairs):
+            a = rho * (s_i @ q)
+            q -= a * y_i
+            alph.append(a)
+        r = h0(q)
+        for (s_i, y_i, rho), a in zip(pairs, reversed(alph)):
+            b = rho * (y_i @ r)
+            r += (a - b) * s_i
+        d = -r
+        if not (g @ d < 0.0):  # not a descent direction: restart from h0
+            pairs = []
+            d = -h0(g)
+        a = line_search_cp_dir(grad, u, d, clip)
+        s_new = a * d
+        u = u + s_new
+        g_new = grad(u)
+        y_new = g_new - g
+        ys = y_new @ s_new
+        if ys > 0.0:
+            pairs.append((s_new, y_new, 1.0 / ys))
+            if len(pairs) > memory:
+                pairs.pop(0)
+        g = g_new
+        its += 1
+        rel = np.linalg.norm(g) / gn0
+    return u, its, rel
+
+
+def lbfgs_load_steps(disc, mu, lam, mask, lift, n_steps, make_h0, memory=5, rtol=1e-8,
+                     max_its=500, u0=None):
+    """Displacement-driven load stepping with L-BFGS at every load level.  Step ``k``
+    starts from the previous solution plus ``lift / n_steps``; ``make_h0(u)`` returns
+    the initial inverse Hessian built at that starting point (the V-cycle on the
+    tangent there).  Returns ``u`` and per-step iteration counts."""
+    N = disc.n_nodes
+    u = np.zeros((N, 3)) if u0 is None else np.asarray(u0, np.float64).copy()
+    lift = np.asarray(lift, np.float64).reshape(N, 3)
+
+    def grad(v):
+        return fem.residual(disc, v.reshape(N, 3), mu, lam, mask).reshape(-1)
+
+    history = []
+    for _ in range(n_steps):
+        u = u + lift / n_steps
+        h0 = make_h0(u)
+        x, its, _ = lbfgs(grad, u.reshape(-1), h0, memory=memory, rtol=rtol, max_its=max_its)
+        u = x.reshape(N, 3)
         history.append(its)
     return u, history
