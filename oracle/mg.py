@@ -232,7 +232,7 @@ def line_search_cp(resid, u, du):
     """Critical-point line search: one secant step on ``g(a) = F(u + a du)^T du``."""
     g0 = resid(u).reshape(-1) @ du.reshape(-1)
     g1 = resid(u + du).reshape(-1) @ du.reshape(-1)
-    if g0 - g1 <= 0.0:
+    if not (g1 - g0 > 0.0):  # secant slope not positive: no critical point ahead
         return 1.0
     return float(np.clip(g0 / (g0 - g1), 0.1, 1.5))
 
@@ -274,7 +274,7 @@ def line_search_cp_dir(grad, u, d, clip=(0.1, 1.5)):
     ``clip=None`` returns the unclipped secant root (exact for a quadratic energy)."""
     g0 = grad(u) @ d
     g1 = grad(u + d) @ d
-    if g0 - g1 <= 0.0:
+    if not (g1 - g0 > 0.0):  # secant slope not positive: no critical point ahead
         return 1.0
     a = g0 / (g0 - g1)
     return a if clip is None else float(np.clip(a, clip[0], clip[1]))

@@ -559,7 +559,8 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
       const double g1 = mg->host[0];
       unsigned fl2 = 0;
       if ((st = hpmg_op_query_flags(fine, stream, &fl2))) return st;  // clears the trial point's flags
-      if (std::isfinite(g1) && !fl2 && g0 - g1 > 0.0) alpha = std::min(1.5, std::max(0.1, g0 / (g0 - g1)));
+      // Secant root of g between 0 and 1 when its secant slope is positive; else 1.
+      if (std::isfinite(g1) && !fl2 && g1 - g0 > 0.0) alpha = std::min(1.5, std::max(0.1, g0 / (g0 - g1)));
       else if (!std::isfinite(g1) || fl2) alpha = 0.5;
     }
     // Accept u + alpha du, halving alpha while the point has an inverted element or a

@@ -1,8 +1,10 @@
 """Pins of the oracle's multigrid pieces and solver drivers (CPU only): interpolation of
 affine fields, the exact-Galerkin identity of coarse operators built on the fine
 quadrature, the closed-form Chebyshev error polynomial, Ritz bounds of the eigenvalue
-estimate, flexible CG against a direct solve, symmetry of the V-cycle, and the
-homogeneous uniaxial-stretch solution of the Newton driver."""
+estimate, flexible CG against a direct solve, symmetry of the V-cycle, the homogeneous
+uniaxial-stretch solution of the Newton driver, and L-BFGS (its iterates equal those of
+CG on a quadratic with exact line search, one step with the exact inverse Hessian, the
+Newton answer on a Neo-Hookean problem)."""
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
@@ -192,3 +194,75 @@ def test_newton_with_pmg_fcg():
         fem.tangent_matrix = orig
     u2, h2 = mg.newton_load_steps(d, MU, LAM, maskf, lift, 2, solve_direct, rtol=1e-9)
     np.testing.assert_allclose(u1, u2, atol=1e-9)
+
+
+def _spd(n, seed):
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((n, n))
+    A = M @ M.T + n * np.eye(n) * 0.1
+    b = rng.standard_normal(n)
+    return A, b
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_lbfgs_iterates_are_cg_iterates_on_a_quadratic(k):
+    """On a strictly convex quadratic with H0 = I, exact line searches and enough
+    memory, (L-)BFGS generates the conjugate-gradient iterates (the BFGS-CG
+    equivalence, Nocedal & Wright, Numerical Optimization, Section 6.4); CG is written out independently here."""
+    A, b = _spd(12, 3)
+    grad = lambda x: A @ x - b
+    x_bfgs, its, _ = mg.lbfgs(grad, np.zeros(12), lambda v: v.copy(), memory=12, rtol=0.0, max_its=k,
+                              clip=None)
+    assert its == k
+    x = np.zeros(12)
+    r = b.copy()
+    p = r.copy()
+    for _ in range(k):
+        Ap = A @ p
+        a = (r @ r) / (p @ Ap)
+        x = x + a * p
+        r_new = r - a * Ap
+        p = r_new + (r_new @ r_new) / (r @ r) * p
+        r = r_new
+    np.testing.assert_allclose(x_bfgs, x, rtol=1e-9, atol=1e-12)
+
+
+def test_lbfgs_converges_in_one_step_with_the_exact_inverse_hessian():
+    A, b = _spd(10, 4)
+    Ainv = np.linalg.inv(A)
+    x, its, rel = mg.lbfgs(lambda v: A @ v - b, np.zeros(10), lambda v: Ainv @ v, rtol=1e-12, clip=None)
+    assert its == 1
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=1e-12)
+
+
+def test_lbfgs_load_steps_reach_the_newton_answer():
+    """Neo-Hookean, Q2 on 2^3 elements, x = 0 clamped, x = 1 face pulled by 0.2 in two
+    load steps: L-BFGS with the tangent inverse at each step's start as H0 converges to
+    the equilibrium the Newton driver finds."""
+    m = inputs.box_mesh(2, 2, jitter=0.05)
+    d = fem.make_disc(m.coords, m.elem_nodes, 3)
+    mask = inputs.face_mask(m, {"x0": (1, 1, 1), "x1": (1, 1, 1)})
+    lift = inputs.affine_lifting(m, (0.2, 0.0, 0.0))
+
+    def make_h0(u):
+        K = fem.apply_bc(fem.tangent_matrix(d, u, MU, LAM), mask).tocsc()
+        lu = spla.splu(K)
+        return lambda v: lu.solve(v)
+
+    u1, h1 = mg.lbfgs_load_steps(d, MU, LAM, mask, lift, 2, make_h0, rtol=1e-11)
+    u2, h2 = mg.newton_load_steps(d, MU, LAM, mask, lift, 2,
+                                  lambda K, rhs: spla.spsolve(K.tocsc(), rhs), rtol=1e-11)
+    np.testing.assert_allclose(u1, u2, atol=1e-9)
+    assert max(h1) <= 30
+
+
+@pytest.mark.parametrize("scale,expect", [(2.0, 0.5), (0.8, 1.25), (1.0, 1.0)])
+def test_line_search_cp_is_exact_on_a_quadratic(scale, expect):
+    """For a linear residual F(u) = A u - b the secant on F(u + a du)^T du is exact: a
+    direction `scale` times the Newton step gets the step length 1 / scale."""
+    A, b = _spd(9, 5)
+    du = scale * np.linalg.solve(A, b)
+    a = mg.line_search_cp(lambda v: A @ v - b, np.zeros(9), du)
+    assert abs(a - expect) < 1e-12
+    a2 = mg.line_search_cp_dir(lambda v: A @ v - b, np.zeros(9), du)
+    assert abs(a2 - expect) < 1e-12
