@@ -266,6 +266,33 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
                       const hpmg_newton_params *params, const double *const *seeds,
                       double *stats, void *stream);
 
+/* L-BFGS with the V-cycle as the initial inverse Hessian and the critical-point line
+ * search (Section III-A; the residual F(u) is the gradient of the strain energy).
+ * Load stepping as in hpmg_newton_solve (step k adds lift / n_steps to u).  At the
+ * start of every load step the state is stored at the lifted point and the V-cycle is
+ * set up there; it then serves as H0 for all iterations of that step (residuals of
+ * the iterations do not overwrite the stored state).  Direction by the two-loop
+ * recursion over the last `memory` pairs s = u_new - u, y = F(u_new) - F(u) (pairs with
+ * y^T s <= 0 are skipped; a non-descent direction drops all pairs).  A step length
+ * whose point has an inverted element is halved (at most 6 times).  Stops when
+ * ||F(u)|| <= rtol ||F(u_start)|| in every load step.  The caller provides a device
+ * workspace of hpmg_lbfgs_workspace_bytes() (256-byte aligned), private to the call.
+ * Statistics (host): stats[0] = total iterations, stats[1] = V-cycles, stats[2] = final
+ * relative residual of the last load step, stats[3] = memory restarts,
+ * stats[4 + k] = iterations of load step k (k < n_steps, at most 60). */
+typedef struct {
+  double rtol;     /* (1e-8) */
+  int max_its;     /* (200) per load step */
+  int memory;      /* (5) stored pairs, 1..32 */
+  int line_search; /* 1: critical-point secant step, clipped to [0.1, 1.5] */
+  int monitor;     /* (0) 1: one line per iteration on stderr */
+} hpmg_lbfgs_params;
+void hpmg_lbfgs_default_params(hpmg_lbfgs_params *p);
+int hpmg_lbfgs_workspace_bytes(hpmg_mg mg, int memory, size_t *bytes);
+int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+                     const hpmg_lbfgs_params *params, const double *const *seeds, void *workspace,
+                     size_t workspace_bytes, double *stats, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -44,6 +44,11 @@ class NewtonParams(C.Structure):
                 ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int)]
 
 
+class LbfgsParams(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("max_its", C.c_int), ("memory", C.c_int),
+                ("line_search", C.c_int), ("monitor", C.c_int)]
+
+
 _VP, _I64, _D, _I = C.c_void_p, C.c_int64, C.c_double, C.c_int
 _SIGS = {
     "hpmg_status_string": ([_I], C.c_char_p),
@@ -85,6 +90,9 @@ _SIGS = {
     "hpmg_fcg_solve": ([_VP, _VP, _VP, _VP, _D, _I, C.POINTER(_I), C.POINTER(_D), _VP], _I),
     "hpmg_newton_default_params": ([C.POINTER(NewtonParams)], None),
     "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
+    "hpmg_lbfgs_default_params": ([C.POINTER(LbfgsParams)], None),
+    "hpmg_lbfgs_workspace_bytes": ([_VP, _I, C.POINTER(C.c_size_t)], _I),
+    "hpmg_lbfgs_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(LbfgsParams), _VP, _VP, C.c_size_t, _VP, _VP], _I),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -409,6 +417,32 @@ class PMG:
                                      _stream())
         s = list(stats)
         res = {"newton_its": int(s[0]), "krylov_its": int(s[1]), "final_rel": s[2], "step_halvings": int(s[3]),
+               "per_step": [int(v) for v in s[4:]]}
+        if st != 0:
+            try:
+                _check(st)
+            except HpmgError as err:
+                raise HpmgError(st, f"{err} (statistics so far: {res})") from None
+        return u, res
+
+    def lbfgs(self, u, lift, n_steps, seeds, rtol=1e-8, max_its=200, memory=5, line_search=True,
+              monitor=False):
+        """L-BFGS load stepping with this V-cycle as the initial inverse Hessian; ``u``
+        (FP64 [N][3]) is updated in place.  Returns ``u`` and a statistics dict."""
+        import torch
+        prm = LbfgsParams()
+        lib().hpmg_lbfgs_default_params(C.byref(prm))
+        prm.rtol, prm.max_its, prm.memory = rtol, max_its, memory
+        prm.line_search, prm.monitor = int(bool(line_search)), int(bool(monitor))
+        nb = C.c_size_t()
+        _check(lib().hpmg_lbfgs_workspace_bytes(self.h, int(memory), C.byref(nb)))
+        ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=u.device)
+        stats = (C.c_double * (4 + n_steps))()
+        st = lib().hpmg_lbfgs_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()), int(n_steps),
+                                    C.byref(prm), self._seed_array(seeds), _p(ws), int(nb.value),
+                                    C.cast(stats, C.c_void_p), _stream())
+        s = list(stats)
+        res = {"iterations": int(s[0]), "vcycles": int(s[1]), "final_rel": s[2], "restarts": int(s[3]),
                "per_step": [int(v) for v in s[4:]]}
         if st != 0:
             try:

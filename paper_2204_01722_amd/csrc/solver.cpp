@@ -3,6 +3,7 @@
 // in the library's kernels; the host reads back the few scalars that decide control
 // flow (CG coefficients, norms) through a pinned buffer.
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstdio>
 #include <string>
@@ -664,6 +665,183 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
   stats[1] = total_lin;
   stats[2] = final_rel;
   stats[3] = cuts;
+  return HPMG_OK;
+}
+
+// ------------------------------------------------------------------------------------
+// L-BFGS with the V-cycle as initial inverse Hessian (Section III-A).
+// ------------------------------------------------------------------------------------
+void hpmg_lbfgs_default_params(hpmg_lbfgs_params *p) {
+  if (!p) return;
+  p->rtol = 1e-8;
+  p->max_its = 200;
+  p->memory = 5;
+  p->line_search = 1;
+  p->monitor = 0;
+}
+
+static size_t lbfgs_bytes(int64_t n, int memory) {
+  const size_t v = ((size_t)n * sizeof(double) + 255) / 256 * 256;
+  return v * (size_t)(2 * memory + 4);
+}
+
+int hpmg_lbfgs_workspace_bytes(hpmg_mg mg, int memory, size_t *bytes) {
+  int st = mg_check(mg, "lbfgs_workspace_bytes");
+  if (st) return st;
+  if (!bytes) return fail(HPMG_ERR_ARG, "lbfgs_workspace_bytes: null output");
+  if (memory < 1 || memory > 32) return fail(HPMG_ERR_ARG, "lbfgs_workspace_bytes: 1 <= memory <= 32");
+  *bytes = lbfgs_bytes(mg->lv[0].n, memory);
+  return HPMG_OK;
+}
+
+int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+                     const hpmg_lbfgs_params *prm, const double *const *seeds, void *workspace,
+                     size_t workspace_bytes, double *stats, void *stream) {
+  int st = mg_check(mg, "lbfgs_solve");
+  if (st) return st;
+  if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "lbfgs_solve: operator is not the mg fine level");
+  if (!u || !lift || !prm || !seeds || !stats || !workspace) return fail(HPMG_ERR_ARG, "lbfgs_solve: null argument");
+  if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "lbfgs_solve: 1 <= n_steps <= 60");
+  const int m = prm->memory;
+  if (m < 1 || m > 32) return fail(HPMG_ERR_ARG, "lbfgs_solve: 1 <= memory <= 32");
+  if (!(prm->rtol > 0.0) || prm->max_its < 1) return fail(HPMG_ERR_ARG, "lbfgs_solve: rtol > 0, max_its >= 1");
+  if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "lbfgs_solve: call qdata_setup first");
+  const int64_t n = mg->lv[0].n;
+  if (workspace_bytes < lbfgs_bytes(n, m)) return fail(HPMG_ERR_WORKSPACE, "lbfgs_solve: workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(HPMG_ERR_WORKSPACE, "lbfgs_solve: workspace not 256-byte aligned");
+  hipStream_t s = S(stream);
+  const size_t vb = ((size_t)n * sizeof(double) + 255) / 256 * 256;
+  char *w = static_cast<char *>(workspace);
+  std::vector<double *> Sv(m), Yv(m);
+  for (int i = 0; i < m; ++i) {
+    Sv[i] = reinterpret_cast<double *>(w + (size_t)i * vb);
+    Yv[i] = reinterpret_cast<double *>(w + (size_t)(m + i) * vb);
+  }
+  double *g = reinterpret_cast<double *>(w + (size_t)(2 * m) * vb);
+  double *q = reinterpret_cast<double *>(w + (size_t)(2 * m + 1) * vb);
+  double *gt = reinterpret_cast<double *>(w + (size_t)(2 * m + 2) * vb);
+  double *ut = reinterpret_cast<double *>(w + (size_t)(2 * m + 3) * vb);
+  double *d = q;  // the direction overwrites the two-loop vector in place
+  auto dot = [&](const double *a, const double *b, double *out) -> int {
+    HPMG_HIP(launch_dot(HPMG_F64, n, a, b, mg->red, mg->scal, s));
+    int e = read_scalars(mg, 1, s);
+    if (e) return e;
+    *out = mg->host[0];
+    return HPMG_OK;
+  };
+  auto gradient = [&](const double *x, double *out, bool store, double *norm, unsigned *flags) -> int {
+    HPMG_HIP(launch_residual(*fine, x, out, store, s));
+    if (store) {
+      fine->state_version++;
+      fine->state_ready = true;
+      fine->state32_ready = false;
+    }
+    int e = dot(out, out, norm);
+    if (e) return e;
+    *norm = std::sqrt(*norm);
+    return hpmg_op_query_flags(fine, stream, flags);
+  };
+  for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;
+  const int64_t v0 = mg->n_vcycles;
+  int total = 0, restarts = 0;
+  double final_rel = 0.0;
+  std::vector<double> rho(m), alph(m);
+  for (int step = 0; step < n_steps; ++step) {
+    HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0 / n_steps, lift, 1.0, u, s));
+    // The V-cycle is built once per load step, on the tangent at the lifted start.
+    double gn = 0.0;
+    unsigned fl = 0;
+    if ((st = gradient(u, g, true, &gn, &fl))) return st;
+    if ((fl & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE)) || !std::isfinite(gn))
+      return fail(HPMG_ERR_NONPOSITIVE_J, "lbfgs_solve: inverted element at the start of a load step");
+    if ((st = do_setup(mg, seeds, s))) return st;
+    const double g0n = gn;
+    int count = 0, head = 0, its = 0;  // pairs stored, slot of the next pair
+    while (g0n > 0.0 && !(gn <= prm->rtol * g0n)) {
+      if (its >= prm->max_its) {
+        stats[0] = total + its;
+        stats[1] = (double)(mg->n_vcycles - v0);
+        stats[2] = gn / g0n;
+        stats[3] = restarts;
+        return fail(HPMG_ERR_NOT_CONVERGED, "lbfgs_solve: iteration limit");
+      }
+      // Two-loop recursion, newest pair first; then H0 = V-cycle; then oldest first.
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, g, 0.0, g, q, s));
+      for (int j = 0; j < count; ++j) {
+        const int i = (head - 1 - j + m) % m;
+        double sq = 0.0;
+        if ((st = dot(Sv[i], q, &sq))) return st;
+        alph[i] = rho[i] * sq;
+        HPMG_HIP(launch_axpby(HPMG_F64, n, -alph[i], Yv[i], 1.0, q, s));
+      }
+      if ((st = vcycle(mg, q, gt, s))) return st;  // r = H0 q, held in gt for now
+      for (int j = count - 1; j >= 0; --j) {
+        const int i = (head - 1 - j + m) % m;
+        double yr = 0.0;
+        if ((st = dot(Yv[i], gt, &yr))) return st;
+        HPMG_HIP(launch_axpby(HPMG_F64, n, alph[i] - rho[i] * yr, Sv[i], 1.0, gt, s));
+      }
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, gt, 0.0, gt, d, s));
+      double gd = 0.0;
+      if ((st = dot(g, d, &gd))) return st;
+      if (!(gd < 0.0)) {  // not a descent direction: forget the pairs, use H0 alone
+        ++restarts;
+        count = head = 0;
+        if ((st = vcycle(mg, g, gt, s))) return st;
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, gt, 0.0, gt, d, s));
+        if ((st = dot(g, d, &gd))) return st;
+        if (!(gd < 0.0)) return fail(HPMG_ERR_BREAKDOWN, "lbfgs_solve: V-cycle gives no descent direction");
+      }
+      double alpha = 1.0;
+      if (prm->line_search) {
+        // Critical-point step: secant root of g(a) = F(u + a d)^T d between 0 and 1.
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 1.0, d, ut, s));
+        double tn = 0.0;
+        unsigned tf = 0;
+        if ((st = gradient(ut, gt, false, &tn, &tf))) return st;
+        double g1 = 0.0;
+        if ((st = dot(gt, d, &g1))) return st;
+        if (std::isfinite(g1) && !tf && g1 - gd > 0.0) alpha = std::min(1.5, std::max(0.1, gd / (gd - g1)));
+        else if (!std::isfinite(g1) || tf) alpha = 0.5;
+      }
+      // Accept u + alpha d, halving alpha while the point is inadmissible.
+      bool ok = false;
+      double tn = 0.0;
+      for (int bt = 0; bt < 7; ++bt) {
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, alpha, d, ut, s));
+        unsigned tf = 0;
+        if ((st = gradient(ut, gt, false, &tn, &tf))) return st;
+        ok = std::isfinite(tn) && !(tf & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE));
+        if (ok) break;
+        alpha *= 0.5;
+      }
+      if (!ok) return fail(HPMG_ERR_NONPOSITIVE_J, "lbfgs_solve: no admissible step length");
+      // New pair s = alpha d, y = F(u_new) - F(u), kept when y^T s > 0.
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, alpha, d, 0.0, d, Sv[head], s));
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, gt, -1.0, g, Yv[head], s));
+      double ys = 0.0;
+      if ((st = dot(Yv[head], Sv[head], &ys))) return st;
+      if (ys > 0.0) {
+        rho[head] = 1.0 / ys;
+        head = (head + 1) % m;
+        count = std::min(count + 1, m);
+      }
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, ut, 0.0, ut, u, s));
+      HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, gt, 0.0, gt, g, s));
+      gn = tn;
+      ++its;
+      if (prm->monitor)
+        std::fprintf(stderr, "[lbfgs] step %d it %d rel %.3e alpha %.3f pairs %d\n", step, its, gn / g0n, alpha,
+                     count);
+    }
+    total += its;
+    stats[4 + step] = its;
+    final_rel = g0n > 0.0 ? gn / g0n : 0.0;
+  }
+  stats[0] = total;
+  stats[1] = (double)(mg->n_vcycles - v0);
+  stats[2] = final_rel;
+  stats[3] = restarts;
   return HPMG_OK;
 }
 

@@ -268,3 +268,38 @@ def test_newton_cuts_the_load_increment():
     print(f"[newton_cut] stats={st}", flush=True)
     assert st["step_halvings"] >= 1
     assert rel(t2n(u), ref) < 1e-7
+
+
+def test_lbfgs_matches_oracle():
+    """L-BFGS with the V-cycle as initial inverse Hessian (Q4 -> Q2 -> Q1, 2^3 elements,
+    x = 0 clamped, x = 1 face pulled by 0.2 in two load steps): the GPU driver takes the
+    same number of iterations per load step as the oracle's L-BFGS with the oracle's
+    V-cycle built at the same points, and both reach the Newton equilibrium."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("lbfgs_oracle")
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(2, 4, jitter=0.05)
+    H = Hierarchy(m, [4, 2, 1], faces=faces)
+    lift_np = inputs.affine_lifting(m, (0.2, 0.0, 0.0))
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    Ps = [omg.prolongation(H.topos[l - 1], H.orders[l - 1] + 1, H.ops[l - 1].n_nodes,
+                           H.topos[l], H.orders[l] + 1, H.ops[l].n_nodes) for l in range(1, 3)]
+    seeds = [t2n(s) for s in H.seeds(7)]
+
+    def make_h0(u):
+        V = omg.VCycle(fem.tangent_matrix(d, u, MU, LAM), Ps, H.masks, seeds, degree=3, coarse_fixed=8)
+        return lambda v: V(v)
+
+    ref, hist = omg.lbfgs_load_steps(d, MU, LAM, H.masks[0], lift_np, 2, make_h0, rtol=1e-10)
+    newton, _ = omg.newton_load_steps(d, MU, LAM, H.masks[0], lift_np, 2,
+                                      lambda K, rhs: spla.spsolve(K.tocsc(), rhs), rtol=1e-11)
+    assert rel(ref, newton) < 1e-8
+    pmg = PMG(H.ops, precision="f64", coarse_fixed_its=8)
+    u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    u, st = pmg.lbfgs(u, _dev(lift_np), 2, H.seeds(7), rtol=1e-10)
+    print(f"[lbfgs] stats={st} oracle_its={hist}", flush=True)
+    assert st["per_step"] == hist
+    assert rel(t2n(u), ref) < 1e-8
+    assert rel(t2n(u), newton) < 1e-8
