@@ -255,6 +255,14 @@ def main():
         variants["q4_residual_f64"] = {"ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9}
         variants["q4_f32_stored"]["hbm_frac"] = (algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 4) /
                                                  (variants["q4_f32_stored"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS)
+        # the initial-configuration (S(E)) forms of the same operator: 19 and 26 scalars
+        q4.op.state_initial(q4.u)
+        for mode, ns in (("initial_native", 19), ("initial_tuned", 26)):
+            t = time_op(q4.apply("f64", mode), args.steps, args.warmup, stream)
+            variants[f"q4_f64_{mode}"] = {
+                "ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9, "scalars_per_point": ns,
+                "hbm_frac": algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 8, nstate=ns) / (t * 1e-3) / 1e9 /
+                HBM_PEAK_GBPS}
         print("[bench] building Q2 43^3 workload", file=sys.stderr, flush=True)
         q2 = Workload(43, 2)
         for prec, mode in (("f64", "stored"), ("f32", "stored"), ("f64", "recompute")):

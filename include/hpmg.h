@@ -48,7 +48,12 @@ typedef enum {
 } hpmg_status;
 
 typedef enum { HPMG_F64 = 0, HPMG_F32 = 1 } hpmg_precision;
-typedef enum { HPMG_STORED = 0, HPMG_RECOMPUTE = 1 } hpmg_mode;
+typedef enum {
+  HPMG_STORED = 0,         /* the 17-scalar current-configuration state (Section III-B) */
+  HPMG_RECOMPUTE = 1,      /* rebuilt from u and the geometric factors */
+  HPMG_INITIAL_NATIVE = 2, /* initial configuration, 19 scalars: W, grad_X xi; grad_X u */
+  HPMG_INITIAL_TUNED = 3   /* initial configuration, 26 scalars: + C^-1, lambda log J */
+} hpmg_mode;
 
 /* Device flag bits reported by hpmg_op_query_flags. */
 #define HPMG_FLAG_NONPOSITIVE_J 1u
@@ -135,7 +140,11 @@ int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void 
  *   accumulation; requires hpmg_state_cast_f32 after the last state update).
  *   mode HPMG_STORED reads the stored linearisation (u unused, may be NULL);
  *   HPMG_RECOMPUTE rebuilds it from u (double [n_nodes][3]) and the geometric
- *   factors (fine operators only, precision HPMG_F64 or HPMG_F32). */
+ *   factors (fine operators only, precision HPMG_F64 or HPMG_F32);
+ *   HPMG_INITIAL_NATIVE / HPMG_INITIAL_TUNED apply the same operator written in the
+ *   initial configuration (S(E) form, Table different-storage) from the geometric
+ *   factors and the linearisation stored by hpmg_state_initial (fine operators,
+ *   HPMG_F64 only). */
 int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, const void *du,
                         void *y, void *stream);
 /* Order-1 coarse operators only (Pc = 2): builds the dense 24 x 24 element matrices
@@ -146,6 +155,15 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
  * instead of the fine-quadrature linearisation.  A new stored linearisation makes them
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
+
+/* Initial-configuration linearisation (Table different-storage, "initial" rows) at u:
+ * grad_X u (9), C^-1 (6, symmetric xx yy zz yz xz xy), lambda log J (1) per point,
+ * written to a caller-owned device buffer of hpmg_state_initial_bytes() bytes (FP64,
+ * [tile][16][ET*Q^3], 256-byte aligned) that the operator then reads in the
+ * HPMG_INITIAL_* Jacobian modes; the buffer must stay allocated while they are used
+ * and is not refreshed by hpmg_residual.  Fine operators only. */
+int hpmg_state_initial_bytes(hpmg_op op, size_t *bytes);
+int hpmg_state_initial(hpmg_op op, const double *u, void *buffer, size_t bytes, void *stream);
 
 /* Casts the stored FP64 linearisation to the FP32 copy used by FP32 applies. */
 int hpmg_state_cast_f32(hpmg_op op, void *stream);

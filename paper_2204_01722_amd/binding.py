@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhpmg.so")
 
 F64, F32 = 0, 1
-STORED, RECOMPUTE = 0, 1
+STORED, RECOMPUTE, INITIAL_NATIVE, INITIAL_TUNED = 0, 1, 2, 3
 FLAG_NONPOSITIVE_J, FLAG_NONFINITE, FLAG_BAD_INDEX = 1, 2, 4
 REDUCE_SCRATCH = 2048
 
@@ -89,6 +89,8 @@ _SIGS = {
     "hpmg_mg_stats": ([_VP, _VP], _I),
     "hpmg_fcg_solve": ([_VP, _VP, _VP, _VP, _D, _I, C.POINTER(_I), C.POINTER(_D), _VP], _I),
     "hpmg_newton_default_params": ([C.POINTER(NewtonParams)], None),
+    "hpmg_state_initial_bytes": ([_VP, C.POINTER(C.c_size_t)], _I),
+    "hpmg_state_initial": ([_VP, _VP, _VP, C.c_size_t, _VP], _I),
     "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
     "hpmg_lbfgs_default_params": ([C.POINTER(LbfgsParams)], None),
     "hpmg_lbfgs_workspace_bytes": ([_VP, _I, C.POINTER(C.c_size_t)], _I),
@@ -148,6 +150,10 @@ def _mode(m):
         return STORED
     if m in (RECOMPUTE, "recompute"):
         return RECOMPUTE
+    if m in (INITIAL_NATIVE, "initial_native"):
+        return INITIAL_NATIVE
+    if m in (INITIAL_TUNED, "initial_tuned"):
+        return INITIAL_TUNED
     raise ValueError(f"bad mode {m!r}")
 
 
@@ -257,6 +263,14 @@ class Operator:
         out = torch.empty(self.n_elem, 10, self.Q ** 3, dtype=torch.float64, device=self.device)
         _check(lib().hpmg_qdata_export(self.h, _p(out), _stream()))
         return out
+
+    def state_initial(self, u):
+        """Stores the initial-configuration linearisation at ``u`` (grad_X u, C^-1,
+        lambda log J) for the ``initial_native`` / ``initial_tuned`` Jacobian modes."""
+        nb = C.c_size_t()
+        _check(lib().hpmg_state_initial_bytes(self.h, C.byref(nb)))
+        self.sinit = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        _check(lib().hpmg_state_initial(self.h, _p(self._in(u)), _p(self.sinit), int(nb.value), _stream()))
 
     def residual(self, u, store_state: bool = True, out=None):
         u = self._in(u)

@@ -343,10 +343,38 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
     if (op->fine) return fail(HPMG_ERR_ARG, "jacobian_apply: recompute mode needs a fine operator");
     if (!u) return fail(HPMG_ERR_ARG, "jacobian_apply: recompute mode needs u");
     if (!op->geo_ready) return fail(HPMG_ERR_ARG, "jacobian_apply: call qdata_setup first");
+  } else if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED) {
+    if (op->fine) return fail(HPMG_ERR_ARG, "jacobian_apply: initial-configuration modes need a fine operator");
+    if (precision != HPMG_F64) return fail(HPMG_ERR_UNSUPPORTED, "jacobian_apply: initial-configuration modes are FP64");
+    if (!op->sinit_ready) return fail(HPMG_ERR_ARG, "jacobian_apply: call hpmg_state_initial first");
+    if (use_atomic_scatter()) return fail(HPMG_ERR_UNSUPPORTED, "jacobian_apply: initial-configuration modes need the record scatter");
   } else {
     return fail(HPMG_ERR_ARG, "jacobian_apply: bad mode");
   }
   HPMG_HIP(launch_jacobian(*op, precision, mode, u, du, y, S(stream)));
+  return HPMG_OK;
+}
+
+int hpmg_state_initial_bytes(hpmg_op op, size_t *bytes) {
+  if (!op || !bytes) return fail(HPMG_ERR_ARG, "state_initial_bytes: null argument");
+  if (op->fine) return fail(HPMG_ERR_ARG, "state_initial_bytes: fine operators only");
+  *bytes = (size_t)op->tiles * NINIT * op->NQ * sizeof(double);
+  return HPMG_OK;
+}
+
+int hpmg_state_initial(hpmg_op op, const double *u, void *buffer, size_t bytes, void *stream) {
+  int st = check_ready(op, "state_initial");
+  if (st) return st;
+  if (op->fine) return fail(HPMG_ERR_ARG, "state_initial: fine operators only");
+  if (!u || !buffer) return fail(HPMG_ERR_ARG, "state_initial: null argument");
+  if (!op->geo_ready) return fail(HPMG_ERR_ARG, "state_initial: call qdata_setup first");
+  size_t need = 0;
+  hpmg_state_initial_bytes(op, &need);
+  if (bytes < need) return fail(HPMG_ERR_WORKSPACE, "state_initial: buffer too small");
+  if (reinterpret_cast<uintptr_t>(buffer) % 256) return fail(HPMG_ERR_WORKSPACE, "state_initial: buffer not 256-byte aligned");
+  op->sinit = static_cast<double *>(buffer);
+  HPMG_HIP(launch_state_initial(*op, u, S(stream)));
+  op->sinit_ready = true;
   return HPMG_OK;
 }
 

@@ -25,7 +25,8 @@ constexpr int tile_threads(int Q) {
 }
 
 constexpr int NGEO = 10;    // W, dxi_k/dX_J (row-major)
-constexpr int NSTATE = 17;  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
+constexpr int NSTATE = 17;
+constexpr int NINIT = 16;   // initial-configuration linearisation: grad_X u (9), C^-1 (6), lambda log J  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
 
 // Reference tables, in the operator's precision, at fixed offsets (max 8 x 8 each).
 constexpr int TAB_B = 0;      // [Q][P] interpolation
@@ -71,6 +72,8 @@ struct hpmg_op_s {
   uint32_t *emap = nullptr;
   double *geo = nullptr;       // fine only
   double *state64 = nullptr;   // fine only
+  double *sinit = nullptr;     // fine only, caller-provided: [tile][16][ET*Q^3] (hpmg_state_initial)
+  bool sinit_ready = false;
   float *state32 = nullptr;    // fine only
   double *scratch = nullptr;   // reductions
   int32_t *csr_off = nullptr;  // node -> incidences (element-local records), [N + 1]
@@ -104,6 +107,7 @@ int ctof_table(int Pf, int Pc, double *M);
 bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
+hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s);
 hipError_t launch_qdata(const hpmg_op_s &op, const double *coords, hipStream_t s);
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s);
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,

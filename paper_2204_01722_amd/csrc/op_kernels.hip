@@ -274,6 +274,100 @@ __device__ __forceinline__ void adjoint_qf(const T (&C)[3][3], const T (&A)[3][3
     for (int a = 0; a < 3; ++a) f[i][a] = W * (s[i][0] * A[a][0] + s[i][1] * A[a][1] + s[i][2] * A[a][2]);
 }
 
+// Jacobian pointwise map in the initial configuration (the S(E) form of the same
+// model, Section V / Table different-storage): with dF = G D = grad_X du,
+//   S  = mu I + (c - mu) C^-1                     (c = lambda log J),
+//   dC = dF^T F + F^T dF,
+//   dS = (mu - c) C^-1 dC C^-1 + (lambda / 2) tr(C^-1 dC) C^-1,
+//   dP = dF S + F dS,   f = W dP D^T.
+// hv holds grad_X u (9, row-major) and, when TUNED, C^-1 (6, symmetric) and c; the
+// "native" form recomputes C^-1 and c from grad_X u (J - 1 without cancellation).
+template <bool TUNED>
+__device__ __forceinline__ void jacobian_qf_initial(const double (&G)[3][3], const double (&gv)[NGEO],
+                                                    const double *hv, double mu, double lam,
+                                                    double (&f)[3][3]) {
+  double D[3][3], H[3][3], dF[3][3], F[3][3], Ci[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      D[k][J] = gv[1 + k * 3 + J];
+      H[k][J] = hv[k * 3 + J];
+    }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      dF[i][J] = G[i][0] * D[0][J] + G[i][1] * D[1][J] + G[i][2] * D[2][J];
+      F[i][J] = (i == J ? 1.0 : 0.0) + H[i][J];
+    }
+  double c;
+  if (TUNED) {
+#pragma unroll
+    for (int I = 0; I < 3; ++I)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) Ci[I][J] = hv[9 + sym_index(I, J)];
+    c = hv[15];
+  } else {
+    const double tr = H[0][0] + H[1][1] + H[2][2];
+    double tr2 = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) tr2 += H[i][j] * H[j][i];
+    const double Jm1 = tr + 0.5 * (tr * tr - tr2) + det3(H);
+    c = lam * log1p(Jm1);
+    double Fi[3][3];
+    inv3(F, 1.0 + Jm1, Fi);
+#pragma unroll
+    for (int I = 0; I < 3; ++I)
+#pragma unroll
+      for (int J = 0; J < 3; ++J) Ci[I][J] = Fi[I][0] * Fi[J][0] + Fi[I][1] * Fi[J][1] + Fi[I][2] * Fi[J][2];
+  }
+  double dC[3][3];
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v += dF[a][I] * F[a][J] + F[a][I] * dF[a][J];
+      dC[I][J] = v;
+    }
+  double M[3][3], tr = 0.0;
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      M[I][J] = Ci[I][0] * dC[0][J] + Ci[I][1] * dC[1][J] + Ci[I][2] * dC[2][J];
+      if (I == J) tr += M[I][J];
+    }
+  double dS[3][3], Sm[3][3];
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      const double e1 = M[I][0] * Ci[0][J] + M[I][1] * Ci[1][J] + M[I][2] * Ci[2][J];
+      dS[I][J] = (mu - c) * e1 + 0.5 * lam * tr * Ci[I][J];
+      Sm[I][J] = (I == J ? mu : 0.0) + (c - mu) * Ci[I][J];
+    }
+  double dP[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) {
+      double v = 0.0;
+#pragma unroll
+      for (int K = 0; K < 3; ++K) v += dF[i][K] * Sm[K][J] + F[i][K] * dS[K][J];
+      dP[i][J] = v;
+    }
+  const double W = gv[0];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[i][k] = W * (dP[i][0] * D[k][0] + dP[i][1] * D[k][1] + dP[i][2] * D[k][2]);
+}
+
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Give
 // every XCD a contiguous range of tiles so neighbouring elements (which share nodes,
 // hence gathered values and atomic targets) run under the same L2.
@@ -569,11 +663,16 @@ __device__ __forceinline__ void line_stage(T *buf, const T *__restrict__ M, int 
   }
 }
 
-template <typename T, int P, int Q>
+// MODE 0: the 17-scalar current-configuration state (T = double or float).
+// MODE 1 / 2: the initial-configuration forms, 19 / 26 scalars (geometry W, grad_X xi
+// + grad_X u [+ C^-1, lambda log J]); T = double.
+template <typename T, int P, int Q, int MODE>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
+    const double *__restrict__ geo, const double *__restrict__ sinit,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
     const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
+  constexpr int NH = MODE == 2 ? NINIT : 9;
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
   // Per element: v [3][Q^3] (du, then its values at the points, then the nodal result)
   // and G [3][3][Q^3] (gradient, then the flux).
@@ -596,11 +695,21 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     v[Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 1)) & 1u) ? T(0) : x1;
     v[2 * Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : x2;
   }
-  T sv[NSTATE];
+  T sv[MODE == 0 ? NSTATE : 1];
+  double gv[MODE == 0 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
   if (live) {
-    const T *s = state + tile * NSTATE * NQ + tq;
+    if constexpr (MODE == 0) {
+      const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
-    for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+    } else {
+      const double *g = geo + tile * NGEO * NQ + tq;
+#pragma unroll
+      for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
+      const double *h = sinit + tile * NINIT * NQ + tq;
+#pragma unroll
+      for (int f = 0; f < NH; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
+    }
   }
   __syncthreads();
   // Interpolation to the points, one direction at a time, in place.
@@ -646,21 +755,25 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   __syncthreads();
   // Quadrature function, one thread per point, flux written over the gradient.
   if (live) {
-    T Gq[3][3], A[3][3], tau[6];
+    T Gq[3][3], f[3][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
       for (int k = 0; k < 3; ++k) Gq[c][k] = G[(c * 3 + k) * Q3 + q];
+    if constexpr (MODE == 0) {
+      T A[3][3], tau[6];
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 3; ++k)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
+        for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
 #pragma unroll
-    for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
-    const T c = sv[15], W = sv[16];
-    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
-    T f[3][3];
-    jacobian_qf(Gq, A, tau, c, W, mu, lam, f);
+      for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
+      const T c = sv[15], W = sv[16];
+      const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+      jacobian_qf(Gq, A, tau, c, W, mu, lam, f);
+    } else {
+      jacobian_qf_initial<MODE == 2>(Gq, gv, hv, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), f);
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -726,6 +839,61 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     o[1] = y1;
     o[2] = y2;
   }
+}
+
+// ------------------------------------------------------------------------------------
+// Initial-configuration linearisation at u: grad_X u (9), C^-1 (6), lambda log J (1)
+// per point, [tile][16][ET*Q^3] (the 26-scalar "tuned" form together with the constant
+// W and grad_X xi; its first 9 fields are the 19-scalar "native" form).
+// ------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_state_initial(
+    const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ geo,
+    const double *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
+    const double *__restrict__ lam_e, double *__restrict__ sinit, unsigned *__restrict__ flags, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  constexpr int S0 = 3 * Q3;
+  __shared__ T sB[Q * P], sD[Q * Q];
+  __shared__ T lds[2 * ET * S0];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
+  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S0;
+  if (live && q < P3) gather_node(u, emap[e * P3 + q], false, a, q, P3);
+  __syncthreads();
+  interp<T, P, Q, 3>(a, b, sB, q, live);
+  if (!live) return;
+  T G[3][3], D[3][3];
+  grad_q<T, Q, 3>(b, sD, q, G);
+  const double *g = geo + tile * NGEO * NQ + tq;
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+  Kin<T> k;
+  kinematics(G, D, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), k);
+  if (!(k.Jm1 > -1.0)) atomicOr(flags, k.Jm1 == k.Jm1 ? HPMG_FLAG_NONPOSITIVE_J : HPMG_FLAG_NONFINITE);
+  T F[3][3], Fi[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[i][j] = (i == j ? 1.0 : 0.0) + k.H[i][j];
+  inv3(F, 1.0 + k.Jm1, Fi);
+  double *o = sinit + tile * NINIT * NQ + tq;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int J = 0; J < 3; ++J) o[(i * 3 + J) * NQ] = k.H[i][J];
+#pragma unroll
+  for (int I = 0; I < 3; ++I)
+#pragma unroll
+    for (int J = I; J < 3; ++J)
+      o[(9 + sym_index(I, J)) * NQ] = Fi[I][0] * Fi[J][0] + Fi[I][1] * Fi[J][1] + Fi[I][2] * Fi[J][2];
+  o[15 * NQ] = k.c;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1446,9 +1614,22 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
                               T *y, T *ev, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
+  if constexpr (std::is_same<T, double>::value) {
+    if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED) {
+      if (!ev) return hipErrorInvalidValue;  // these kernels only write element records
+      if (mode == HPMG_INITIAL_NATIVE)
+        k_jacobian_lines<T, P, Q, 1><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+      else
+        k_jacobian_lines<T, P, Q, 2><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+      return hipGetLastError();
+    }
+  }
   if (mode == HPMG_STORED && ev && use_line_kernels()) {
-    k_jacobian_lines<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
-                                                                        f.mu_e, f.lam_e, ev, op.E);
+    k_jacobian_lines<T, P, Q, 0><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, nullptr, nullptr,
+                                                                           tab, f.mu, f.lam, f.mu_e, f.lam_e, ev,
+                                                                           op.E);
     return hipGetLastError();
   }
   if (mode == HPMG_STORED) {
@@ -1567,6 +1748,19 @@ hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipS
     hipError_t e = hipGetLastError();                                                            \
     if (e != hipSuccess) return e;                                                               \
     return launch_sum(op.E, op.scratch, op.scratch + op.E, psi, s);                              \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s) {
+#define X(p, q)                                                                                      \
+  if (op.P == p && op.Q == q) {                                                                      \
+    k_state_initial<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, \
+                                                                   op.lam, op.mu_e, op.lam_e, op.sinit, \
+                                                                   op.flags, op.E);                  \
+    return hipGetLastError();                                                                        \
   }
   HPMG_PQ_LIST(X)
 #undef X

@@ -96,6 +96,33 @@ def test_residual_and_jacobian(n, p, q, faces):
     assert op.query_flags() == 0
 
 
+@pytest.mark.parametrize("n,p,q,faces", CASES + [(2, 4, 5, "materials")])
+def test_initial_configuration_jacobian(n, p, q, faces):
+    """The S(E) (initial-configuration) forms of the same Jacobian, with 19 and 26
+    stored scalars, against the oracle's first-Piola tangent."""
+    print_case("initial_configuration", n=n, p=p, q=q, faces=faces)
+    mu_e = lam_e = None
+    if faces == "materials":
+        m0 = inputs.box_mesh(n, p, jitter=0.05)
+        mu_e, lam_e = inputs.loguniform_materials(m0.n_elem, seed=4)
+        faces = {"x0": (1, 1, 1)}
+    m, H = _setup(n, p, faces=faces, q=q, mu_e=mu_e, lam_e=lam_e)
+    d, mask, u, du = _oracle_problem(m, q, faces)
+    mu = MU if mu_e is None else mu_e
+    lam = LAM if lam_e is None else lam_e
+    op = H.fine
+    ut, dut = _dev(u), _dev(du)
+    op.state_initial(ut)
+    y_ref = fem.jacobian_apply(d, u, du, mu, lam, mask)
+    for mode in ("initial_native", "initial_tuned"):
+        y = op.jacobian(dut, "f64", mode)
+        assert rel(t2n(y), y_ref) < TOL64, (mode, rel(t2n(y), y_ref))
+        if mask is not None:
+            mb = mask.astype(bool)
+            assert np.all(t2n(y)[mb] == du[mb])
+    assert op.query_flags() == 0
+
+
 @pytest.mark.parametrize("n,p,q,faces", CASES[:5])
 def test_diagonal(n, p, q, faces):
     print_case("diagonal", n=n, p=p, q=q, faces=faces)
