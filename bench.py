@@ -257,7 +257,7 @@ def main():
                                                  (variants["q4_f32_stored"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS)
         # the initial-configuration (S(E)) forms of the same operator: 19 and 26 scalars
         q4.op.state_initial(q4.u)
-        for mode, ns in (("initial_native", 19), ("initial_tuned", 26)):
+        for mode, ns in (("initial_native", 19), ("initial_tuned", 26), ("current_20", 20)):
             t = time_op(q4.apply("f64", mode), args.steps, args.warmup, stream)
             variants[f"q4_f64_{mode}"] = {
                 "ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9, "scalars_per_point": ns,

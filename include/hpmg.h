@@ -52,7 +52,8 @@ typedef enum {
   HPMG_STORED = 0,         /* the 17-scalar current-configuration state (Section III-B) */
   HPMG_RECOMPUTE = 1,      /* rebuilt from u and the geometric factors */
   HPMG_INITIAL_NATIVE = 2, /* initial configuration, 19 scalars: W, grad_X xi; grad_X u */
-  HPMG_INITIAL_TUNED = 3   /* initial configuration, 26 scalars: + C^-1, lambda log J */
+  HPMG_INITIAL_TUNED = 3,  /* initial configuration, 26 scalars: + C^-1, lambda log J */
+  HPMG_CURRENT_20 = 4      /* current configuration, 20 scalars: dxi/dx, J, grad_X u, W */
 } hpmg_mode;
 
 /* Device flag bits reported by hpmg_op_query_flags. */
@@ -143,8 +144,9 @@ int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void 
  *   factors (fine operators only, precision HPMG_F64 or HPMG_F32);
  *   HPMG_INITIAL_NATIVE / HPMG_INITIAL_TUNED apply the same operator written in the
  *   initial configuration (S(E) form, Table different-storage) from the geometric
- *   factors and the linearisation stored by hpmg_state_initial (fine operators,
- *   HPMG_F64 only). */
+ *   factors and the linearisation stored by hpmg_state_initial; HPMG_CURRENT_20 applies
+ *   the current-configuration form from dxi/dx, J, grad_X u and W (tau and lambda log J
+ *   rebuilt per point) from the same buffer (fine operators, HPMG_F64 only). */
 int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, const void *du,
                         void *y, void *stream);
 /* Order-1 coarse operators only (Pc = 2): builds the dense 24 x 24 element matrices
@@ -156,12 +158,13 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
 
-/* Initial-configuration linearisation (Table different-storage, "initial" rows) at u:
- * grad_X u (9), C^-1 (6, symmetric xx yy zz yz xz xy), lambda log J (1) per point,
+/* Alternative linearisations (Table different-storage) at u: grad_X u (9), C^-1 (6,
+ * symmetric xx yy zz yz xz xy), lambda log J (1), dxi/dx (9), J - 1 (1) per point,
  * written to a caller-owned device buffer of hpmg_state_initial_bytes() bytes (FP64,
- * [tile][16][ET*Q^3], 256-byte aligned) that the operator then reads in the
- * HPMG_INITIAL_* Jacobian modes; the buffer must stay allocated while they are used
- * and is not refreshed by hpmg_residual.  Fine operators only. */
+ * [tile][26][ET*Q^3], 256-byte aligned) that the operator then reads in the
+ * HPMG_INITIAL_NATIVE, HPMG_INITIAL_TUNED and HPMG_CURRENT_20 Jacobian modes (each
+ * reads only its own fields); the buffer must stay allocated while they are used and
+ * is not refreshed by hpmg_residual.  Fine operators only. */
 int hpmg_state_initial_bytes(hpmg_op op, size_t *bytes);
 int hpmg_state_initial(hpmg_op op, const double *u, void *buffer, size_t bytes, void *stream);
 

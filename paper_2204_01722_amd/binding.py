@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhpmg.so")
 
 F64, F32 = 0, 1
-STORED, RECOMPUTE, INITIAL_NATIVE, INITIAL_TUNED = 0, 1, 2, 3
+STORED, RECOMPUTE, INITIAL_NATIVE, INITIAL_TUNED, CURRENT_20 = 0, 1, 2, 3, 4
 FLAG_NONPOSITIVE_J, FLAG_NONFINITE, FLAG_BAD_INDEX = 1, 2, 4
 REDUCE_SCRATCH = 2048
 
@@ -154,6 +154,8 @@ def _mode(m):
         return INITIAL_NATIVE
     if m in (INITIAL_TUNED, "initial_tuned"):
         return INITIAL_TUNED
+    if m in (CURRENT_20, "current_20"):
+        return CURRENT_20
     raise ValueError(f"bad mode {m!r}")
 
 
@@ -265,8 +267,9 @@ class Operator:
         return out
 
     def state_initial(self, u):
-        """Stores the initial-configuration linearisation at ``u`` (grad_X u, C^-1,
-        lambda log J) for the ``initial_native`` / ``initial_tuned`` Jacobian modes."""
+        """Stores the alternative linearisations at ``u`` (grad_X u, C^-1, lambda log J,
+        dxi/dx, J - 1) for the ``initial_native``, ``initial_tuned`` and ``current_20``
+        Jacobian modes."""
         nb = C.c_size_t()
         _check(lib().hpmg_state_initial_bytes(self.h, C.byref(nb)))
         self.sinit = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)

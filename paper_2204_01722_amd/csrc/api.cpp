@@ -343,7 +343,7 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
     if (op->fine) return fail(HPMG_ERR_ARG, "jacobian_apply: recompute mode needs a fine operator");
     if (!u) return fail(HPMG_ERR_ARG, "jacobian_apply: recompute mode needs u");
     if (!op->geo_ready) return fail(HPMG_ERR_ARG, "jacobian_apply: call qdata_setup first");
-  } else if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED) {
+  } else if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
     if (op->fine) return fail(HPMG_ERR_ARG, "jacobian_apply: initial-configuration modes need a fine operator");
     if (precision != HPMG_F64) return fail(HPMG_ERR_UNSUPPORTED, "jacobian_apply: initial-configuration modes are FP64");
     if (!op->sinit_ready) return fail(HPMG_ERR_ARG, "jacobian_apply: call hpmg_state_initial first");

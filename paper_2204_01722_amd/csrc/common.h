@@ -26,7 +26,7 @@ constexpr int tile_threads(int Q) {
 
 constexpr int NGEO = 10;    // W, dxi_k/dX_J (row-major)
 constexpr int NSTATE = 17;
-constexpr int NINIT = 16;   // initial-configuration linearisation: grad_X u (9), C^-1 (6), lambda log J  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
+constexpr int NINIT = 26;   // grad_X u (9), C^-1 (6), lambda log J (1), dxi/dx (9), J - 1 (1)  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
 
 // Reference tables, in the operator's precision, at fixed offsets (max 8 x 8 each).
 constexpr int TAB_B = 0;      // [Q][P] interpolation
@@ -72,7 +72,7 @@ struct hpmg_op_s {
   uint32_t *emap = nullptr;
   double *geo = nullptr;       // fine only
   double *state64 = nullptr;   // fine only
-  double *sinit = nullptr;     // fine only, caller-provided: [tile][16][ET*Q^3] (hpmg_state_initial)
+  double *sinit = nullptr;     // fine only, caller-provided: [tile][26][ET*Q^3] (hpmg_state_initial)
   bool sinit_ready = false;
   float *state32 = nullptr;    // fine only
   double *scratch = nullptr;   // reductions

@@ -666,13 +666,15 @@ __device__ __forceinline__ void line_stage(T *buf, const T *__restrict__ M, int 
 // MODE 0: the 17-scalar current-configuration state (T = double or float).
 // MODE 1 / 2: the initial-configuration forms, 19 / 26 scalars (geometry W, grad_X xi
 // + grad_X u [+ C^-1, lambda log J]); T = double.
+// MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
+// lambda log J are rebuilt from grad_X u and J; T = double.
 template <typename T, int P, int Q, int MODE>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const double *__restrict__ geo, const double *__restrict__ sinit,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
     const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
-  constexpr int NH = MODE == 2 ? NINIT : 9;
+  constexpr int NH = MODE == 2 ? 16 : MODE == 3 ? 19 : 9;
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
   // Per element: v [3][Q^3] (du, then its values at the points, then the nodal result)
   // and G [3][3][Q^3] (gradient, then the flux).
@@ -696,12 +698,19 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     v[2 * Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : x2;
   }
   T sv[MODE == 0 ? NSTATE : 1];
-  double gv[MODE == 0 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
+  double gv[MODE == 0 ? 1 : MODE == 3 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
   if (live) {
     if constexpr (MODE == 0) {
       const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
       for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+    } else if constexpr (MODE == 3) {
+      gv[0] = __builtin_nontemporal_load(geo + tile * NGEO * NQ + tq);  // W only
+      const double *h = sinit + tile * NINIT * NQ + tq;
+#pragma unroll
+      for (int f = 0; f < 9; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
+#pragma unroll
+      for (int f = 0; f < 10; ++f) hv[9 + f] = __builtin_nontemporal_load(h + (16 + f) * NQ);
     } else {
       const double *g = geo + tile * NGEO * NQ + tq;
 #pragma unroll
@@ -771,6 +780,22 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
       const T c = sv[15], W = sv[16];
       const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
       jacobian_qf(Gq, A, tau, c, W, mu, lam, f);
+    } else if constexpr (MODE == 3) {
+      const double mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
+      double A[3][3], tau[6];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[k][j] = hv[9 + k * 3 + j];
+      const double c = lam * log1p(hv[18]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i; j < 3; ++j) {
+          const double hh = hv[i * 3] * hv[j * 3] + hv[i * 3 + 1] * hv[j * 3 + 1] + hv[i * 3 + 2] * hv[j * 3 + 2];
+          tau[sym_index(i, j)] = mu * (hv[i * 3 + j] + hv[j * 3 + i] + hh) + (i == j ? c : 0.0);
+        }
+      jacobian_qf(Gq, A, tau, c, gv[0], mu, lam, f);
     } else {
       jacobian_qf_initial<MODE == 2>(Gq, gv, hv, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), f);
     }
@@ -842,9 +867,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
 }
 
 // ------------------------------------------------------------------------------------
-// Initial-configuration linearisation at u: grad_X u (9), C^-1 (6), lambda log J (1)
-// per point, [tile][16][ET*Q^3] (the 26-scalar "tuned" form together with the constant
-// W and grad_X xi; its first 9 fields are the 19-scalar "native" form).
+// Alternative linearisations at u, per point, [tile][26][ET*Q^3]: grad_X u (9),
+// C^-1 (6), lambda log J (1), dxi/dx (9), J - 1 (1).  With the constant W and
+// grad_X xi, fields 0-8 are the 19-scalar initial-configuration "native" form, 0-15 the
+// 26-scalar "tuned" form; fields 0-8 and 16-25 with W are the 20-scalar current-
+// configuration form (dxi/dx, J, grad_X u, W).
 // ------------------------------------------------------------------------------------
 template <int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_state_initial(
@@ -894,6 +921,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_state_initial(
     for (int J = I; J < 3; ++J)
       o[(9 + sym_index(I, J)) * NQ] = Fi[I][0] * Fi[J][0] + Fi[I][1] * Fi[J][1] + Fi[I][2] * Fi[J][2];
   o[15 * NQ] = k.c;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) o[(16 + a * 3 + j) * NQ] = k.A[a][j];
+  o[25 * NQ] = k.Jm1;
 }
 
 // ------------------------------------------------------------------------------------
@@ -1615,13 +1647,16 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
   if constexpr (std::is_same<T, double>::value) {
-    if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED) {
+    if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
       if (!ev) return hipErrorInvalidValue;  // these kernels only write element records
       if (mode == HPMG_INITIAL_NATIVE)
         k_jacobian_lines<T, P, Q, 1><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
             op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
-      else
+      else if (mode == HPMG_INITIAL_TUNED)
         k_jacobian_lines<T, P, Q, 2><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+      else
+        k_jacobian_lines<T, P, Q, 3><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
             op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
       return hipGetLastError();
     }

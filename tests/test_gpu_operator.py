@@ -99,7 +99,8 @@ def test_residual_and_jacobian(n, p, q, faces):
 @pytest.mark.parametrize("n,p,q,faces", CASES + [(2, 4, 5, "materials")])
 def test_initial_configuration_jacobian(n, p, q, faces):
     """The S(E) (initial-configuration) forms of the same Jacobian, with 19 and 26
-    stored scalars, against the oracle's first-Piola tangent."""
+    stored scalars, and the 20-scalar current-configuration form, against the oracle's
+    first-Piola tangent."""
     print_case("initial_configuration", n=n, p=p, q=q, faces=faces)
     mu_e = lam_e = None
     if faces == "materials":
@@ -114,7 +115,7 @@ def test_initial_configuration_jacobian(n, p, q, faces):
     ut, dut = _dev(u), _dev(du)
     op.state_initial(ut)
     y_ref = fem.jacobian_apply(d, u, du, mu, lam, mask)
-    for mode in ("initial_native", "initial_tuned"):
+    for mode in ("initial_native", "initial_tuned", "current_20"):
         y = op.jacobian(dut, "f64", mode)
         assert rel(t2n(y), y_ref) < TOL64, (mode, rel(t2n(y), y_ref))
         if mask is not None:
