@@ -24,6 +24,9 @@ Readings taken where the paper is silent:
 * Newton stops on the 2-norm of the residual relative to the load step's first one;
   the line search takes one secant step for ``F(u + a du)^T du = 0`` from ``a = 0, 1``
   and clips ``a`` to ``[0.1, 1.5]`` (``a = 1`` if the secant slope is not positive);
+* a rediscretised coarse level evaluates the operator of its own order on its own
+  (p_c + 1)^3 Gauss points at the coarse interpolant of u (the fine field evaluated at
+  the coarse nodes), instead of the Galerkin product;
 * L-BFGS (Section III-A: the V-cycle as "initial inverse Hessian", same critical-point
   line search) uses the textbook two-loop recursion over the last ``memory`` pairs
   ``s = u_new - u``, ``y = F(u_new) - F(u)``, skips pairs with ``y^T s <= 0``, and
@@ -62,6 +65,18 @@ def prolongation(elem_f, Pf, Nf, elem_c, Pc, Nc):
     C = np.concatenate([3 * cols + i for i in range(3)])
     V = np.concatenate([v, v, v])
     return sp.csr_matrix((V, (R, C)), shape=(3 * Nf, 3 * Nc))
+
+
+def inject(u_f, elem_f, Pf, elem_c, Pc, Nc):
+    """Coarse nodal values of a fine field for a rediscretised coarse level: the fine
+    finite-element function evaluated at each coarse node (its plain definition; for
+    nested node sets it is the fine value at the coinciding node).  ``[Nc][3]``."""
+    vals = eval_3d(Pf, node_positions_3d(Pc))            # [Pc^3][Pf^3]
+    u_f = np.asarray(u_f, np.float64).reshape(-1, 3)
+    out = np.zeros((Nc, 3))
+    for e in range(len(elem_f)):
+        out[np.asarray(elem_c[e])] = vals @ u_f[np.asarray(elem_f[e])]
+    return out
 
 
 def galerkin(K_f, Pm):
@@ -151,16 +166,20 @@ class VCycle:
 
     ``ops[0]`` is the finest Dirichlet-modified operator; ``prolongs[l]`` maps level
     ``l+1`` to level ``l``; ``masks[l]`` are the level masks.  Coarse operators are
-    Galerkin products with the masks re-applied (identity on constrained rows)."""
+    Galerkin products with the masks re-applied (identity on constrained rows), or the
+    given rediscretised operators ``coarse_raw`` (levels 1, 2, ...)."""
 
     def __init__(self, K_fine_raw, prolongs, masks, seeds, degree=3, lo=0.1, hi=1.1,
                  lanczos_its=10, coarse_rtol=1e-3, coarse_maxit=10000, coarse_fixed=None,
-                 lam_override=None):
+                 lam_override=None, coarse_raw=None):
         self.prolongs = prolongs
         self.masks = [None if m is None else np.asarray(m, np.float64).reshape(-1) for m in masks]
         raw = [K_fine_raw.tocsr()]
-        for Pm in prolongs:
-            raw.append(galerkin(raw[-1], Pm))
+        if coarse_raw is not None:       # rediscretised coarse operators, one per level
+            raw += [K.tocsr() for K in coarse_raw]
+        else:
+            for Pm in prolongs:
+                raw.append(galerkin(raw[-1], Pm))
         self.ops = [fem.apply_bc(K, None if m is None else m.reshape(-1, 3))
                     for K, m in zip(raw, self.masks)]
         self.dinv = [1.0 / K.diagonal() for K in self.ops]

@@ -266,3 +266,40 @@ def test_line_search_cp_is_exact_on_a_quadratic(scale, expect):
     assert abs(a - expect) < 1e-12
     a2 = mg.line_search_cp_dir(lambda v: A @ v - b, np.zeros(9), du)
     assert abs(a2 - expect) < 1e-12
+
+
+@pytest.mark.parametrize("pf,pc", [(2, 1), (4, 2), (4, 1)])
+def test_rediscretised_coarse_operator_equals_galerkin_for_linear_elasticity(pf, pc):
+    """On affine elements at u = 0 the integrand of the coarse stiffness is a polynomial
+    that both the fine and the coarse Gauss rules integrate exactly, so the
+    rediscretised coarse operator (own order, own (p_c + 1)^3 points) equals the
+    Galerkin product P^T K P."""
+    mf, mc, Pm = _levels(2, pf, pc, jitter=0.0)
+    df = fem.make_disc(mf.coords, mf.elem_nodes, pf + 1)
+    dc = fem.make_disc(mc.coords, mc.elem_nodes, pc + 1)
+    Kf = fem.tangent_matrix(df, np.zeros((mf.n_nodes, 3)), MU, LAM)
+    Kc = fem.tangent_matrix(dc, np.zeros((mc.n_nodes, 3)), MU, LAM)
+    G = mg.galerkin(Kf, Pm)
+    assert abs(Kc - G).max() < 1e-12 * abs(G).max()
+
+
+@pytest.mark.parametrize("pf,pc", [(2, 1), (4, 2), (3, 1)])
+def test_injection_is_exact_for_affine_fields_and_picks_coinciding_nodes(pf, pc):
+    mf, mc, _ = _levels(2, pf, pc, jitter=0.07)
+    A = np.array([[0.3, -0.1, 0.2], [0.05, 0.4, -0.2], [0.1, 0.0, -0.3]])
+    u_f = mf.coords @ A.T + np.array([0.1, -0.2, 0.3])
+    u_c = mg.inject(u_f, mf.elem_nodes, mf.P, mc.elem_nodes, mc.P, mc.n_nodes)
+    np.testing.assert_allclose(u_c, mc.coords @ A.T + np.array([0.1, -0.2, 0.3]), atol=1e-13)
+    # a non-affine field: coarse vertices coincide with fine vertices
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal((mf.n_nodes, 3))
+    wc = mg.inject(w, mf.elem_nodes, mf.P, mc.elem_nodes, mc.P, mc.n_nodes)
+    s = (pf + 1 - 1) // (pc + 1 - 1)
+    for e in range(mf.n_elem):
+        for a3 in range(pc + 1):
+            for a2 in range(pc + 1):
+                for a1 in range(pc + 1):
+                    ic = mc.elem_nodes[e][a1 + (pc + 1) * (a2 + (pc + 1) * a3)]
+                    f_idx = s * a1 + (pf + 1) * (s * a2 + (pf + 1) * s * a3)
+                    if pc == 1 or pf % 2 == 0:
+                        np.testing.assert_allclose(wc[ic], w[mf.elem_nodes[e][f_idx]], atol=1e-12)
