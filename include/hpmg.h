@@ -228,13 +228,23 @@ typedef struct {
 } hpmg_mg_params;
 
 void hpmg_mg_default_params(hpmg_mg_params *p);
-/* levels[0] is the fine operator, levels[l+1] a coarse operator of levels[0] with a
- * lower order; the last level is solved by Jacobi-PCG.  Handles are borrowed. */
+/* levels[0] is the fine operator; the coarse levels, of decreasing order, are either
+ * all coarse operators of levels[0] (Galerkin: they share its quadrature and state,
+ * Section III-B) or all stand-alone operators on the same elements with their own
+ * order, quadrature and geometry ("rediscretised": their linearisations are stored at
+ * the injected field by hpmg_mg_set_state; needs nested node sets: order 1, or order 2
+ * below an even order).  The last level is solved by Jacobi-PCG.  Handles are
+ * borrowed. */
 int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *params,
                    hpmg_mg *out);
 void hpmg_mg_destroy(hpmg_mg mg);
 int hpmg_mg_workspace_bytes(hpmg_mg mg, size_t *bytes);
 int hpmg_mg_bind_workspace(hpmg_mg mg, void *workspace, size_t bytes);
+/* Rediscretised levels only (a no-op otherwise): injects u (device double
+ * [n_nodes][3] of levels[0]) level by level and stores each level's linearisation
+ * there (a residual evaluation per level).  Call before hpmg_mg_setup whenever the
+ * fine linearisation changes; the Newton and L-BFGS drivers do it themselves. */
+int hpmg_mg_set_state(hpmg_mg mg, const double *u, void *stream);
 /* Per-linearisation setup: FP32 cast of the state (mixed precision), level diagonals
  * and lambda_max of D^{-1}A per smoothed level from `lanczos_its` Jacobi-PCG
  * iterations on the caller's rough vectors seeds[l] (device double [n_nodes_l][3],

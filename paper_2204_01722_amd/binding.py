@@ -91,6 +91,7 @@ _SIGS = {
     "hpmg_newton_default_params": ([C.POINTER(NewtonParams)], None),
     "hpmg_state_initial_bytes": ([_VP, C.POINTER(C.c_size_t)], _I),
     "hpmg_state_initial": ([_VP, _VP, _VP, C.c_size_t, _VP], _I),
+    "hpmg_mg_set_state": ([_VP, _VP, _VP], _I),
     "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
     "hpmg_lbfgs_default_params": ([C.POINTER(LbfgsParams)], None),
     "hpmg_lbfgs_workspace_bytes": ([_VP, _I, C.POINTER(C.c_size_t)], _I),
@@ -441,6 +442,11 @@ class PMG:
             except HpmgError as err:
                 raise HpmgError(st, f"{err} (statistics so far: {res})") from None
         return u, res
+
+    def set_state(self, u):
+        """Stores the linearisations of rediscretised coarse levels at the injection of
+        ``u`` (no-op for Galerkin levels)."""
+        _check(lib().hpmg_mg_set_state(self.h, _p(u.contiguous()), _stream()))
 
     def lbfgs(self, u, lift, n_steps, seeds, rtol=1e-8, max_its=200, memory=5, line_search=True,
               monitor=False):

@@ -107,6 +107,7 @@ int ctof_table(int Pf, int Pc, double *M);
 bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
+hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, double *uc, hipStream_t s);
 hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s);
 hipError_t launch_qdata(const hpmg_op_s &op, const double *coords, hipStream_t s);
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s);

@@ -23,6 +23,11 @@ struct Level {
   int64_t n = 0;  // scalars (3 * nodes)
   void *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *z = nullptr, *dinv = nullptr;
   double lam = 0.0;
+  // rediscretised level: node map into the next finer level (nested node sets) and
+  // the injected displacement its linearisation is stored at
+  bool redisc = false;
+  int32_t *inj = nullptr;
+  double *ustate = nullptr;
 };
 
 }  // namespace
@@ -69,6 +74,11 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
     L.t = take(nb);
     L.z = take(nb);
     L.dinv = take(nb);
+  }
+  for (Level &L : mg->lv) {
+    if (!L.redisc) continue;
+    L.inj = reinterpret_cast<int32_t *>(take((size_t)(L.n / 3) * sizeof(int32_t)));
+    L.ustate = reinterpret_cast<double *>(take((size_t)L.n * sizeof(double)));
   }
   const size_t nf = (size_t)mg->lv[0].n * sizeof(double);
   mg->fr = reinterpret_cast<double *>(take(nf));
@@ -269,14 +279,45 @@ int mg_check(hpmg_mg_s *mg, const char *fn) {
   return HPMG_OK;
 }
 
+bool has_redisc(const hpmg_mg_s *mg) { return mg->lv.size() > 1 && mg->lv[1].redisc; }
+
+// Stores the linearisation of every rediscretised level at the injection of u.
+int set_state(hpmg_mg_s *mg, const double *u, hipStream_t s) {
+  const double *src = u;
+  for (size_t l = 1; l < mg->lv.size(); ++l) {
+    Level &L = mg->lv[l];
+    if (!L.redisc) continue;
+    HPMG_HIP(launch_inject(L.n / 3, L.inj, src, L.ustate, s));
+    hpmg_op_s *o = L.op;
+    if (!o->geo_ready) return fail(HPMG_ERR_ARG, "mg_set_state: call qdata_setup on every rediscretised level");
+    HPMG_HIP(launch_residual(*o, L.ustate, mg->fr, true, s));
+    o->state_version++;
+    o->state_ready = true;
+    o->state32_ready = false;
+    unsigned fl = 0;
+    int st = hpmg_op_query_flags(o, s, &fl);
+    if (st) return st;
+    if (fl & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE))
+      return fail(HPMG_ERR_NONPOSITIVE_J, "mg_set_state: inverted element on a rediscretised level");
+    src = L.ustate;
+  }
+  return HPMG_OK;
+}
+
 int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
   int st;
   const int prec = prec_of(mg);
   hpmg_op_s *fine = mg->lv[0].op;
-  if (!fine->state_ready) return fail(HPMG_ERR_ARG, "mg_setup: no stored linearisation on the fine operator");
-  if (prec == HPMG_F32) {
-    HPMG_HIP(launch_cast_state((int64_t)fine->tiles * fine->NQ * NSTATE, fine->state64, fine->state32, s));
-    fine->state32_ready = true;
+  for (Level &L : mg->lv) {
+    hpmg_op_s *o = L.op;
+    if (o->fine) continue;  // Galerkin coarse level: shares the fine state
+    if (!o->state_ready)
+      return fail(HPMG_ERR_ARG, L.redisc ? "mg_setup: rediscretised level without state (hpmg_mg_set_state)"
+                                         : "mg_setup: no stored linearisation on the fine operator");
+    if (prec == HPMG_F32) {
+      HPMG_HIP(launch_cast_state((int64_t)o->tiles * o->NQ * NSTATE, o->state64, o->state32, s));
+      o->state32_ready = true;
+    }
   }
   for (Level &L : mg->lv) {
     HPMG_HIP(launch_diagonal(*L.op, prec, L.dinv, s));
@@ -394,10 +435,30 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
     return fail(HPMG_ERR_ARG, "mg_create: bad smoother or coarse-solver parameters");
   const hpmg_op_s *f = levels[0];
   if (!f || f->fine) return fail(HPMG_ERR_ARG, "mg_create: levels[0] must be a fine operator");
+  // Coarse levels are either all Galerkin (coarse operators of levels[0], sharing its
+  // state) or all rediscretised (operators of their own order and quadrature on the
+  // same elements, their state stored at the injected field by hpmg_mg_set_state).
+  const bool redisc = levels[1] && !levels[1]->fine;
   for (int l = 1; l < n_levels; ++l) {
-    if (!levels[l] || levels[l]->fine != f)
-      return fail(HPMG_ERR_ARG, "mg_create: coarse levels must be coarse operators of levels[0]");
+    if (!levels[l]) return fail(HPMG_ERR_ARG, "mg_create: null level");
+    if (redisc ? (levels[l]->fine != nullptr) : (levels[l]->fine != f))
+      return fail(HPMG_ERR_ARG, "mg_create: coarse levels must all be coarse operators of levels[0] or all "
+                                "stand-alone (rediscretised) operators");
     if (levels[l]->P >= levels[l - 1]->P) return fail(HPMG_ERR_ARG, "mg_create: orders must decrease");
+    if (redisc) {
+      if (levels[l]->E != f->E) return fail(HPMG_ERR_SHAPE, "mg_create: rediscretised levels need the same elements");
+      const int Pf = levels[l - 1]->P, Pc = levels[l]->P;
+      double gf[16], gc[16];
+      if (tabulate(Pf, Pf, nullptr, nullptr, nullptr, nullptr, nullptr, gf) ||
+          tabulate(Pc, Pc, nullptr, nullptr, nullptr, nullptr, nullptr, gc))
+        return fail(HPMG_ERR_ARG, "mg_create: bad order");
+      bool nested = (Pf - 1) % (Pc - 1) == 0;
+      const int st = nested ? (Pf - 1) / (Pc - 1) : 1;
+      for (int a = 0; nested && a < Pc; ++a) nested = std::fabs(gf[st * a] - gc[a]) < 1e-13;
+      if (!nested)
+        return fail(HPMG_ERR_UNSUPPORTED, "mg_create: rediscretised levels need nested node sets (order "
+                                          "p_c = 1, or p_c = 2 below an even order)");
+    }
   }
   hpmg_mg_s *mg = new hpmg_mg_s();
   mg->prm = *params;
@@ -405,6 +466,7 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
     Level L;
     L.op = levels[l];
     L.n = 3 * levels[l]->N;
+    L.redisc = l > 0 && redisc;
     mg->lv.push_back(L);
   }
   if (hipHostMalloc((void **)&mg->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
@@ -435,7 +497,41 @@ int hpmg_mg_bind_workspace(hpmg_mg mg, void *ws, size_t bytes) {
   mg->bytes = bytes;
   mg_layout(mg, mg->ws);
   mg->setup_done = 0;
+  // Injection maps of rediscretised levels: coarse local node (a1, a2, a3) of an
+  // element sits at fine local node (s a1, s a2, s a3), s = (Pf - 1) / (Pc - 1).
+  for (size_t l = 1; l < mg->lv.size(); ++l) {
+    Level &L = mg->lv[l];
+    if (!L.redisc) continue;
+    const hpmg_op_s &F = *mg->lv[l - 1].op, &Cc = *L.op;
+    const int Pf = F.P, Pc = Cc.P, st = (Pf - 1) / (Pc - 1);
+    const int64_t nf = F.E * Pf * Pf * Pf, nc = Cc.E * Pc * Pc * Pc;
+    std::vector<int32_t> ef(nf), ec(nc), map(Cc.N, -1);
+    HPMG_HIP(hipMemcpy(ef.data(), F.elem_nodes, nf * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HPMG_HIP(hipMemcpy(ec.data(), Cc.elem_nodes, nc * sizeof(int32_t), hipMemcpyDeviceToHost));
+    for (int64_t e = 0; e < Cc.E; ++e)
+      for (int a3 = 0; a3 < Pc; ++a3)
+        for (int a2 = 0; a2 < Pc; ++a2)
+          for (int a1 = 0; a1 < Pc; ++a1) {
+            const int32_t c = ec[e * Pc * Pc * Pc + a1 + Pc * (a2 + Pc * a3)];
+            const int32_t fn = ef[e * Pf * Pf * Pf + st * a1 + Pf * (st * a2 + Pf * st * a3)];
+            if (c < 0 || c >= Cc.N || fn < 0 || fn >= F.N) return fail(HPMG_ERR_SHAPE, "mg_bind_workspace: bad node id");
+            if (map[c] >= 0 && map[c] != fn)
+              return fail(HPMG_ERR_SHAPE, "mg_bind_workspace: coarse node maps to two fine nodes");
+            map[c] = fn;
+          }
+    for (int64_t c = 0; c < Cc.N; ++c)
+      if (map[c] < 0) return fail(HPMG_ERR_SHAPE, "mg_bind_workspace: coarse node in no element");
+    HPMG_HIP(hipMemcpy(L.inj, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
   return HPMG_OK;
+}
+
+int hpmg_mg_set_state(hpmg_mg mg, const double *u, void *stream) {
+  int st = mg_check(mg, "mg_set_state");
+  if (st) return st;
+  if (!u) return fail(HPMG_ERR_ARG, "mg_set_state: null u");
+  if (!has_redisc(mg)) return HPMG_OK;
+  return set_state(mg, u, S(stream));
 }
 
 int hpmg_mg_setup(hpmg_mg mg, const double *const *seeds, void *stream) {
@@ -537,6 +633,9 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
   int its = 0;
   while (f0 > 0.0 && !(fn <= prm->rtol * f0)) {
     if (its >= prm->max_newton) return fail(HPMG_ERR_NOT_CONVERGED, "newton: iteration limit");
+    // the fine state belongs to the previous converged point in the predictor
+    // iteration (saved in nu0), to u afterwards
+    if (has_redisc(mg) && (st = set_state(mg, its == 0 ? mg->nu0 : u, s))) return st;
     if ((st = do_setup(mg, seeds, s))) return st;
     HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, F, 0.0, F, ut, s));
     HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
@@ -754,6 +853,7 @@ int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, in
     if ((st = gradient(u, g, true, &gn, &fl))) return st;
     if ((fl & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE)) || !std::isfinite(gn))
       return fail(HPMG_ERR_NONPOSITIVE_J, "lbfgs_solve: inverted element at the start of a load step");
+    if (has_redisc(mg) && (st = set_state(mg, u, s))) return st;
     if ((st = do_setup(mg, seeds, s))) return st;
     const double g0n = gn;
     int count = 0, head = 0, its = 0;  // pairs stored, slot of the next pair

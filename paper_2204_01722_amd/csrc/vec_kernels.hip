@@ -305,6 +305,16 @@ hipError_t launch_init_bc(int prec, int64_t nn, const uint8_t *mask, const void 
            (k_init_bc<float><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (const float *)x, (float *)y)));
 }
 
+__global__ void k_inject(int64_t nc, const int32_t *__restrict__ map, const double *__restrict__ uf,
+                         double *__restrict__ uc) {
+  GRID_STRIDE(i, 3 * nc) { uc[i] = uf[(int64_t)map[i / 3] * 3 + i % 3]; }
+}
+
+hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, double *uc, hipStream_t s) {
+  k_inject<<<grid_for(3 * nc), BS, 0, s>>>(nc, map, uf, uc);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_bc_one(int prec, int64_t nn, const uint8_t *mask, void *y, hipStream_t s) {
   DISPATCH(prec, (k_fill_bc_one<double><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (double *)y)),
            (k_fill_bc_one<float><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (float *)y)));

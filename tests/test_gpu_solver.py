@@ -303,3 +303,68 @@ def test_lbfgs_matches_oracle():
     assert st["per_step"] == hist
     assert rel(t2n(u), ref) < 1e-8
     assert rel(t2n(u), newton) < 1e-8
+
+
+@pytest.mark.parametrize("n,orders,faces", [
+    (2, [4, 2, 1], {"x0": (1, 1, 1), "x1": (1, 1, 1)}),
+    ((3, 2, 2), [2, 1], {"x0": (1, 1, 1)}),
+])
+def test_rediscretised_vcycle_matches_oracle(n, orders, faces):
+    """Coarse levels of their own order and Gauss points, linearised at the injected
+    field, against the oracle V-cycle with the same rediscretised operators."""
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("vcycle_rediscretised", n=n, orders=orders)
+    m = inputs.box_mesh(n, orders[0], jitter=0.05)
+    H = Hierarchy(m, orders, faces=faces, rediscretize=True)
+    u = inputs.config1_u(m, amplitude=0.05)
+    ut = _dev(u)
+    H.fine.residual(ut, store_state=True)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    Ps, Kc, uprev, topo_prev, P_prev = [], [], u, m.elem_nodes, m.P
+    for l in range(1, len(orders)):
+        mc = inputs.box_mesh(n, orders[l], jitter=0.05)
+        Ps.append(omg.prolongation(H.topos[l - 1], H.orders[l - 1] + 1, H.ops[l - 1].n_nodes,
+                                   H.topos[l], H.orders[l] + 1, H.ops[l].n_nodes))
+        uc = omg.inject(uprev, topo_prev, P_prev, mc.elem_nodes, mc.P, mc.n_nodes)
+        Kc.append(fem.tangent_matrix(fem.make_disc(mc.coords, mc.elem_nodes, mc.P), uc, MU, LAM))
+        uprev, topo_prev, P_prev = uc, mc.elem_nodes, mc.P
+    seeds = [t2n(s) for s in H.seeds(7)]
+    V = omg.VCycle(fem.tangent_matrix(d, u, MU, LAM), Ps, H.masks, seeds, degree=3, coarse_fixed=8,
+                   coarse_raw=Kc)
+    fr = 1.0 - H.masks[0].reshape(-1)
+    r = inputs.random_vector(m.n_nodes, 21).reshape(-1) * fr
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        pmg = PMG(H.ops, precision=prec, coarse_fixed_its=8)
+        pmg.set_state(ut)
+        pmg.setup(H.seeds(7))
+        for l in range(len(orders) - 1):
+            lam, _ = pmg.info(l)
+            assert abs(lam - V.lam[l]) <= (1e-10 if prec == "f64" else 1e-4) * V.lam[l], (l, lam, V.lam[l])
+        z = t2n(pmg.vcycle(_dev(r.reshape(-1, 3))))
+        assert rel(z, V(r)) < tol, (prec, rel(z, V(r)))
+
+
+def test_newton_with_rediscretised_levels():
+    """The preconditioner changes, the equilibrium does not: Newton with rediscretised
+    coarse levels reaches the oracle's Newton answer (Q4 -> Q2 -> Q1, 2^3 elements)."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("newton_rediscretised")
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(2, 4, jitter=0.05)
+    H = Hierarchy(m, [4, 2, 1], faces=faces, rediscretize=True)
+    lift_np = inputs.affine_lifting(m, (0.2, 0.0, 0.0))
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    ref, _ = omg.newton_load_steps(d, MU, LAM, H.masks[0], lift_np, 2,
+                                   lambda K, rhs: spla.spsolve(K.tocsc(), rhs), rtol=1e-11)
+    for prec in ("f64", "f32"):
+        pmg = PMG(H.ops, precision=prec)
+        u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+        u, st = pmg.newton(u, _dev(lift_np), 2, H.seeds(7), rtol=1e-10, lin_rtol=1e-4)
+        print(f"[newton_rediscretised] precision={prec} stats={st}", flush=True)
+        assert rel(t2n(u), ref) < 1e-8, (prec, rel(t2n(u), ref))
+    u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    u, st = PMG(H.ops, precision="f32").lbfgs(u, _dev(lift_np), 2, H.seeds(7), rtol=1e-10)
+    assert rel(t2n(u), ref) < 1e-8
