@@ -12,8 +12,10 @@ textbook initial-configuration form:
   ``tau F^{-T}`` for the paper's Kirchhoff stress ``tau = 2 mu e + lambda log J I``;
 * tangent ``A_{iJkL} = dP_{iJ}/dF_{kL}
   = mu d_ik d_JL + (mu - lambda log J) Finv_{Jk} Finv_{Li} + lambda Finv_{Ji} Finv_{Lk}``;
-* residual ``r_{a,i} = sum_e sum_q W P_{iJ} dphi_a/dX_J`` (internal force; the
-  workloads carry no body force or traction);
+* residual ``r_{a,i} = sum_e sum_q W P_{iJ} dphi_a/dX_J`` (internal force);
+* external dead loads (eq. variational-form, right-hand side): body force
+  ``int v . rho0 g dV`` and traction ``int v . t dA`` on reference element faces, both
+  constant in u, so the Jacobian is unchanged;
 * energy ``Psi = sum W psi``, ``psi = lambda/2 (log J)^2 - mu log J + mu tr e`` with
   ``e = (H + H^T + H H^T)/2``.
 
@@ -31,7 +33,7 @@ from dataclasses import dataclass
 import numpy as np
 import scipy.sparse as sp
 
-from .basis import tensor_3d
+from .basis import gauss, gll_nodes, lagrange, tensor_3d
 
 
 @dataclass
@@ -269,3 +271,55 @@ def residual_vjp(disc: Disc, u, w, mu, lam, mask=None, chunk=4096):
         mub[sl] = np.einsum("eq,eqiJ,eqiJ->e", W, Gw, F - FinvT)
         lamb[sl] = np.einsum("eq,eq,eqiJ,eqiJ->e", W, logJ, Gw, FinvT)
     return ub, mub, lamb
+
+
+# --------------------------------------------------------------------------------------
+# External dead loads (eq. variational-form, right-hand side)
+# --------------------------------------------------------------------------------------
+def body_force_load(disc: Disc, rho_g):
+    """``b_{a,i} = int phi_a (rho0 g)_i dV`` over the reference volume, ``[N][3]``, for a
+    constant body force per unit reference volume ``rho_g`` (3-vector)."""
+    W, _, _ = geometry(disc)                                   # [e][q]
+    per = np.einsum("eq,qa->ea", W, disc.T["Phi"])             # int phi_a dV per element
+    out = np.zeros((disc.n_nodes, 3))
+    np.add.at(out, disc.elem_nodes.reshape(-1), per.reshape(-1)[:, None] * np.asarray(rho_g)[None, :])
+    return out
+
+
+# Local faces of a hexahedron: (reference direction held fixed, its value).
+FACES = [(0, -1.0), (0, 1.0), (1, -1.0), (1, 1.0), (2, -1.0), (2, 1.0)]
+
+
+def traction_load(coords, elem_nodes, P, Q, faces, t):
+    """``b_{a,i} = int phi_a t_i dA`` over the listed element faces of the reference
+    configuration, ``[N][3]``: ``faces`` holds ``(element, local face)`` pairs with
+    local faces 0..5 = xi_1 = -1, +1, xi_2 = -1, +1, xi_3 = -1, +1; ``t`` is a constant
+    traction per unit reference area.  The area element is ``|dX/dxi_s x dX/dxi_r|``
+    for the two in-face directions (s, r), Gauss rule with ``Q`` points per direction."""
+    nodes = gll_nodes(P)
+    xq, wq = gauss(Q)
+    coords = np.asarray(coords, np.float64)
+    out = np.zeros((coords.shape[0], 3))
+    for e, f in faces:
+        d, v = FACES[f]
+        s_dir, r_dir = [k for k in range(3) if k != d]
+        Le, _ = lagrange(nodes, np.array([v]))                 # 1D values at the fixed end
+        Xe = coords[np.asarray(elem_nodes[e])]                 # [P^3][3]
+        for i in range(Q):
+            for j in range(Q):
+                xi = np.zeros(3)
+                xi[d], xi[s_dir], xi[r_dir] = v, xq[i], xq[j]
+                val = np.ones(P ** 3)
+                der = {s_dir: np.ones(P ** 3), r_dir: np.ones(P ** 3)}
+                for k in range(3):
+                    Lk, Dk = lagrange(nodes, np.array([xi[k]]))
+                    idx = np.arange(P ** 3)
+                    ak = (idx // P ** k) % P
+                    val = val * Lk[0, ak]
+                    for m in (s_dir, r_dir):
+                        der[m] = der[m] * (Dk[0, ak] if m == k else Lk[0, ak])
+                ts = der[s_dir] @ Xe
+                tr = der[r_dir] @ Xe
+                dA = np.linalg.norm(np.cross(ts, tr)) * wq[i] * wq[j]
+                np.add.at(out, np.asarray(elem_nodes[e]), val[:, None] * np.asarray(t)[None, :] * dA)
+    return out

@@ -257,9 +257,11 @@ def line_search_cp(resid, u, du):
 
 
 def newton_load_steps(disc, mu, lam, mask, lift, n_steps, linear_solve, rtol=1e-8,
-                      max_newton=20, u0=None, line_search=True):
-    """Displacement-driven load stepping.  ``lift`` holds the full imposed displacement
-    on constrained components and an extension of it elsewhere; step ``k`` starts from
+                      max_newton=20, u0=None, line_search=True, f_ext=None):
+    """Displacement-driven load stepping, with an optional external load ``f_ext``
+    ramped by the same fraction (``F(u) = r(u) - (k / n_steps) f_ext`` in step ``k``).
+    ``lift`` holds the full imposed displacement on constrained components and an
+    extension of it elsewhere; step ``k`` starts from
     the previous solution plus ``lift / n_steps`` and runs Newton with homogeneous
     corrections on constrained components.  ``linear_solve(K_bc, rhs)`` returns the
     Newton correction.  Returns ``u`` and per-step Newton iteration counts."""
@@ -268,10 +270,16 @@ def newton_load_steps(disc, mu, lam, mask, lift, n_steps, linear_solve, rtol=1e-
     lift = np.asarray(lift, np.float64).reshape(N, 3)
     history = []
 
-    def resid(v):
-        return fem.residual(disc, v, mu, lam, mask)
+    fe = None if f_ext is None else np.asarray(f_ext, np.float64).reshape(N, 3) * (
+        1.0 if mask is None else 1.0 - np.asarray(mask, np.float64).reshape(N, 3))
+    load = [0.0]
 
-    for _ in range(n_steps):
+    def resid(v):
+        r = fem.residual(disc, v, mu, lam, mask)
+        return r if fe is None else r - load[0] * fe
+
+    for k in range(n_steps):
+        load[0] = (k + 1) / n_steps
         u = u + lift / n_steps
         F = resid(u)
         f0 = np.linalg.norm(F)

@@ -3,11 +3,13 @@
 Each check is fixed by mathematics rather than by the oracle itself: exact volume,
 equilibrium identities of the patch test, rigid motions, objectivity, finite
 differences of the energy and of the residual, the linear-elastic limit assembled from
-the textbook strain-displacement form, and a 50-digit evaluation of ``J - 1``."""
+the textbook strain-displacement form, a 50-digit evaluation of ``J - 1``, and the
+totals and the uniaxial-stress solution of external body-force and traction loads."""
 import numpy as np
 import pytest
+import scipy.sparse.linalg as spla
 
-from oracle import fem
+from oracle import fem, mg
 from paper_2204_01722_amd import inputs
 
 MU, LAM = inputs.lame(1.0, 0.3)
@@ -273,3 +275,49 @@ def test_vjp_mu_bar_is_mixed_energy_derivative():
     a0, b0 = dpsi(u - h * w)
     np.testing.assert_allclose((a1 - a0) / (2 * h), mub, rtol=1e-7, atol=1e-10)
     np.testing.assert_allclose((b1 - b0) / (2 * h), lamb, rtol=1e-6, atol=1e-10)
+
+
+def _x1_faces(m):
+    nx, ny, nz = m.n if not np.isscalar(m.n) else (m.n,) * 3
+    return [(ex + nx * (ey + ny * ez), 1) for ez in range(nz) for ey in range(ny) for ex in [nx - 1]]
+
+
+@pytest.mark.parametrize("p", [1, 2, 4])
+def test_external_load_totals(p):
+    """The nodal loads of a constant body force sum to rho0 g times the volume, those of
+    a constant traction on the x = L_x face to t times that face's area."""
+    L = (2.0, 1.0, 0.5)
+    m = inputs.box_mesh(2, p, L=L, jitter=0.08)
+    d = fem.make_disc(m.coords, m.elem_nodes, p + 1)
+    g = np.array([0.3, -1.2, 0.7])
+    b = fem.body_force_load(d, g)
+    np.testing.assert_allclose(b.sum(axis=0), g * np.prod(L), rtol=1e-13)
+    t = np.array([0.25, 0.5, -1.0])
+    tl = fem.traction_load(m.coords, m.elem_nodes, p + 1, p + 1, _x1_faces(m), t)
+    np.testing.assert_allclose(tl.sum(axis=0), t * L[1] * L[2], rtol=1e-13)
+    # only nodes on the loaded face carry traction loads
+    off = np.abs(m.coords[:, 0] - L[0]) > 1e-12
+    assert np.abs(tl[off]).max() == 0.0
+
+
+def test_uniaxial_stress_by_traction():
+    """Roller faces x = 0, y = 0, z = 0, traction T on x = 1: the finite-element solution
+    is the homogeneous uniaxial-stress state F = diag(l1, l2, l2) with P11 = T and
+    P22 = 0 (closed form of the compressible neo-Hookean first Piola stress)."""
+    from scipy.optimize import fsolve
+    T = 0.12
+    m = inputs.box_mesh(2, 2, jitter=0.08)
+    d = fem.make_disc(m.coords, m.elem_nodes, 3)
+    mask = inputs.face_mask(m, {"x0": (1, 0, 0), "y0": (0, 1, 0), "z0": (0, 0, 1)})
+    f_ext = fem.traction_load(m.coords, m.elem_nodes, 3, 3, _x1_faces(m), np.array([T, 0.0, 0.0]))
+    u, hist = mg.newton_load_steps(d, MU, LAM, mask, np.zeros((m.n_nodes, 3)), 3,
+                                   lambda K, rhs: spla.spsolve(K.tocsc(), rhs), rtol=1e-12, f_ext=f_ext)
+
+    def eqs(x):
+        l1, l2 = x
+        lj = np.log(l1 * l2 * l2)
+        return [MU * (l1 - 1 / l1) + LAM * lj / l1 - T, MU * (l2 - 1 / l2) + LAM * lj / l2]
+    l1, l2 = fsolve(eqs, [1.1, 0.97], xtol=1e-13)
+    exact = m.coords * np.array([l1 - 1.0, l2 - 1.0, l2 - 1.0])
+    np.testing.assert_allclose(u, exact, atol=1e-10)
+    assert l1 > 1.05 and l2 < 1.0
