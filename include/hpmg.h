@@ -158,6 +158,19 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
 
+/* External dead loads (eq. variational-form, right-hand side): f_ext = int phi rho0 g dV
+ * + int phi t dA over the listed element faces, constant per unit reference volume and
+ * area.  rho_g (host double[3]) may be NULL (no body force); faces are given by element
+ * (device int32 [n_faces]) and local face (device int32 [n_faces]: 0..5 = xi_1 = -1, +1,
+ * xi_2 = -1, +1, xi_3 = -1, +1) with coords (device double [n_nodes][3]) and traction
+ * (host double[3]).  Constrained components of f_ext are 0.  Sums are in a fixed order.
+ * The workspace (hpmg_external_load_workspace_bytes, 256-byte aligned) is needed only
+ * when n_faces > 0.  Fine operators; synchronises `stream`. */
+int hpmg_external_load_workspace_bytes(hpmg_op op, int64_t n_faces, size_t *bytes);
+int hpmg_external_load(hpmg_op op, const double *rho_g, const double *coords, int64_t n_faces,
+                       const int32_t *face_elem, const int32_t *face_id, const double *traction,
+                       void *workspace, size_t bytes, double *f_ext, void *stream);
+
 /* Alternative linearisations (Table different-storage) at u: grad_X u (9), C^-1 (6,
  * symmetric xx yy zz yz xz xy), lambda log J (1), dxi/dx (9), J - 1 (1) per point,
  * written to a caller-owned device buffer of hpmg_state_initial_bytes() bytes (FP64,
@@ -270,8 +283,9 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
 
 /* a15: Newton with load stepping and the critical-point line search (Section III-A).
  * Step k = 1..n_steps adds lift / n_steps to u (lift holds the full imposed displacement
- * on constrained components and an extension elsewhere) and iterates until
- * ||F(u)|| <= rtol ||F(u_start)||.  The first correction of a load increment uses the
+ * on constrained components and an extension elsewhere) and iterates on
+ * F(u) = r(u) - (k / n_steps) f_ext (f_ext: external dead load from hpmg_external_load,
+ * or NULL) until ||F(u)|| <= rtol ||F(u_start)||.  The first correction of a load increment uses the
  * tangent of the previous converged state (an Euler predictor), later ones the tangent
  * at the current iterate.  Linear solves: FCG + V-cycle to lin_rtol (a negative-
  * curvature breakdown truncates the solve and the line search takes the direction found
@@ -293,13 +307,14 @@ typedef struct {
                        relative residual, FCG iterations and outcome, step length */
 } hpmg_newton_params;
 void hpmg_newton_default_params(hpmg_newton_params *p);
-int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
-                      const hpmg_newton_params *params, const double *const *seeds,
+int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext,
+                      int n_steps, const hpmg_newton_params *params, const double *const *seeds,
                       double *stats, void *stream);
 
 /* L-BFGS with the V-cycle as the initial inverse Hessian and the critical-point line
  * search (Section III-A; the residual F(u) is the gradient of the strain energy).
- * Load stepping as in hpmg_newton_solve (step k adds lift / n_steps to u).  At the
+ * Load stepping as in hpmg_newton_solve (step k adds lift / n_steps to u and k / n_steps
+ * of the external load f_ext, which may be NULL).  At the
  * start of every load step the state is stored at the lifted point and the V-cycle is
  * set up there; it then serves as H0 for all iterations of that step (residuals of
  * the iterations do not overwrite the stored state).  Direction by the two-loop
@@ -320,9 +335,9 @@ typedef struct {
 } hpmg_lbfgs_params;
 void hpmg_lbfgs_default_params(hpmg_lbfgs_params *p);
 int hpmg_lbfgs_workspace_bytes(hpmg_mg mg, int memory, size_t *bytes);
-int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
-                     const hpmg_lbfgs_params *params, const double *const *seeds, void *workspace,
-                     size_t workspace_bytes, double *stats, void *stream);
+int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext,
+                     int n_steps, const hpmg_lbfgs_params *params, const double *const *seeds,
+                     void *workspace, size_t workspace_bytes, double *stats, void *stream);
 
 #ifdef __cplusplus
 }

@@ -92,10 +92,13 @@ _SIGS = {
     "hpmg_state_initial_bytes": ([_VP, C.POINTER(C.c_size_t)], _I),
     "hpmg_state_initial": ([_VP, _VP, _VP, C.c_size_t, _VP], _I),
     "hpmg_mg_set_state": ([_VP, _VP, _VP], _I),
-    "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
+    "hpmg_newton_solve": ([_VP, _VP, _VP, _VP, _VP, _I, C.POINTER(NewtonParams), _VP, _VP, _VP], _I),
+    "hpmg_external_load_workspace_bytes": ([_VP, _I64, C.POINTER(C.c_size_t)], _I),
+    "hpmg_external_load": ([_VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, C.c_size_t, _VP, _VP], _I),
     "hpmg_lbfgs_default_params": ([C.POINTER(LbfgsParams)], None),
     "hpmg_lbfgs_workspace_bytes": ([_VP, _I, C.POINTER(C.c_size_t)], _I),
-    "hpmg_lbfgs_solve": ([_VP, _VP, _VP, _VP, _I, C.POINTER(LbfgsParams), _VP, _VP, C.c_size_t, _VP, _VP], _I),
+    "hpmg_lbfgs_solve": ([_VP, _VP, _VP, _VP, _VP, _I, C.POINTER(LbfgsParams), _VP, _VP, C.c_size_t, _VP, _VP],
+                         _I),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -267,6 +270,30 @@ class Operator:
         _check(lib().hpmg_qdata_export(self.h, _p(out), _stream()))
         return out
 
+    def external_load(self, rho_g=None, coords=None, faces=None, traction=None):
+        """External dead load ``f_ext`` ([N][3] FP64): body force ``rho_g`` per unit
+        reference volume plus a constant ``traction`` on ``faces`` (pairs (element,
+        local face 0..5)); constrained components 0."""
+        import numpy as np
+        nf = 0 if faces is None else len(faces)
+        f = self._vec(torch.float64)
+        fe = fi = ws = None
+        nb = C.c_size_t(0)
+        if nf:
+            fa = np.asarray(faces, np.int32).reshape(nf, 2)
+            fe = torch.from_numpy(np.ascontiguousarray(fa[:, 0])).to(self.device)
+            fi = torch.from_numpy(np.ascontiguousarray(fa[:, 1])).to(self.device)
+            _check(lib().hpmg_external_load_workspace_bytes(self.h, nf, C.byref(nb)))
+            ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
+        g = None if rho_g is None else (C.c_double * 3)(*[float(v) for v in rho_g])
+        t = None if traction is None else (C.c_double * 3)(*[float(v) for v in traction])
+        _check(lib().hpmg_external_load(self.h, None if g is None else C.cast(g, C.c_void_p),
+                                        None if coords is None else _p(coords.contiguous()), nf,
+                                        None if fe is None else _p(fe), None if fi is None else _p(fi),
+                                        None if t is None else C.cast(t, C.c_void_p),
+                                        None if ws is None else _p(ws), int(nb.value), _p(f), _stream()))
+        return f
+
     def state_initial(self, u):
         """Stores the alternative linearisations at ``u`` (grad_X u, C^-1, lambda log J,
         dxi/dx, J - 1) for the ``initial_native``, ``initial_tuned`` and ``current_20``
@@ -423,14 +450,15 @@ class PMG:
         return x, int(its.value), float(rel.value)
 
     def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
-               line_search=True, monitor=False):
+               line_search=True, monitor=False, f_ext=None):
         prm = NewtonParams()
         lib().hpmg_newton_default_params(C.byref(prm))
         prm.rtol, prm.max_newton, prm.lin_rtol = rtol, max_newton, lin_rtol
         prm.lin_maxit, prm.line_search = lin_maxit, int(bool(line_search))
         prm.monitor = int(bool(monitor))
         stats = (C.c_double * (4 + n_steps))()
-        st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()), int(n_steps),
+        st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()),
+                                     None if f_ext is None else _p(f_ext.contiguous()), int(n_steps),
                                      C.byref(prm), self._seed_array(seeds), C.cast(stats, C.c_void_p),
                                      _stream())
         s = list(stats)
@@ -449,7 +477,7 @@ class PMG:
         _check(lib().hpmg_mg_set_state(self.h, _p(u.contiguous()), _stream()))
 
     def lbfgs(self, u, lift, n_steps, seeds, rtol=1e-8, max_its=200, memory=5, line_search=True,
-              monitor=False):
+              monitor=False, f_ext=None):
         """L-BFGS load stepping with this V-cycle as the initial inverse Hessian; ``u``
         (FP64 [N][3]) is updated in place.  Returns ``u`` and a statistics dict."""
         import torch
@@ -461,7 +489,8 @@ class PMG:
         _check(lib().hpmg_lbfgs_workspace_bytes(self.h, int(memory), C.byref(nb)))
         ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=u.device)
         stats = (C.c_double * (4 + n_steps))()
-        st = lib().hpmg_lbfgs_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()), int(n_steps),
+        st = lib().hpmg_lbfgs_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()),
+                                    None if f_ext is None else _p(f_ext.contiguous()), int(n_steps),
                                     C.byref(prm), self._seed_array(seeds), _p(ws), int(nb.value),
                                     C.cast(stats, C.c_void_p), _stream())
         s = list(stats)

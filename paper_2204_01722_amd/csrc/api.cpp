@@ -355,6 +355,71 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
   return HPMG_OK;
 }
 
+static size_t ext_layout(const hpmg_op_s *op, int64_t nf, size_t *o_rec, size_t *o_node, size_t *o_off,
+                         size_t *o_inc, size_t *o_tmp) {
+  const int64_t P2 = (int64_t)op->P * op->P;
+  size_t o = 0;
+  *o_rec = o; o += align256((size_t)nf * P2 * 3 * sizeof(double));
+  *o_node = o; o += align256((size_t)nf * P2 * sizeof(int32_t));
+  *o_off = o; o += align256(((size_t)op->N + 1) * sizeof(int32_t));
+  *o_inc = o; o += align256((size_t)nf * P2 * sizeof(int32_t));
+  *o_tmp = o; o += align256((size_t)op->N * 3 * sizeof(double));
+  return o;
+}
+
+int hpmg_external_load_workspace_bytes(hpmg_op op, int64_t n_faces, size_t *bytes) {
+  if (!op || !bytes || n_faces < 0) return fail(HPMG_ERR_ARG, "external_load_workspace_bytes: bad argument");
+  size_t a, b, c, d, e;
+  *bytes = ext_layout(op, n_faces, &a, &b, &c, &d, &e);
+  return HPMG_OK;
+}
+
+int hpmg_external_load(hpmg_op op, const double *rho_g, const double *coords, int64_t n_faces,
+                       const int32_t *face_elem, const int32_t *face_id, const double *traction,
+                       void *workspace, size_t bytes, double *f_ext, void *stream) {
+  int st = check_ready(op, "external_load");
+  if (st) return st;
+  if (op->fine) return fail(HPMG_ERR_ARG, "external_load: fine operators only");
+  if (!f_ext || n_faces < 0) return fail(HPMG_ERR_ARG, "external_load: bad argument");
+  if (n_faces > 0 && (!coords || !face_elem || !face_id || !traction))
+    return fail(HPMG_ERR_ARG, "external_load: faces need coords, face lists and a traction");
+  if (rho_g && !op->geo_ready) return fail(HPMG_ERR_ARG, "external_load: call qdata_setup first");
+  size_t o_rec, o_node, o_off, o_inc, o_tmp;
+  const size_t need = ext_layout(op, n_faces, &o_rec, &o_node, &o_off, &o_inc, &o_tmp);
+  if (n_faces > 0 && (!workspace || bytes < need)) return fail(HPMG_ERR_WORKSPACE, "external_load: workspace too small");
+  if (workspace && reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(HPMG_ERR_WORKSPACE, "external_load: workspace not 256-byte aligned");
+  hipStream_t s = S(stream);
+  const double zero[3] = {0.0, 0.0, 0.0};
+  // body force (records of every element, assembled with the operator's incidence
+  // lists; constrained components 0)
+  HPMG_HIP(launch_body_load(*op, rho_g ? rho_g : zero, f_ext, s));
+  if (n_faces == 0) return HPMG_OK;
+  char *w = static_cast<char *>(workspace);
+  double *rec = reinterpret_cast<double *>(w + o_rec), *tmp = reinterpret_cast<double *>(w + o_tmp);
+  int32_t *rnode = reinterpret_cast<int32_t *>(w + o_node), *off = reinterpret_cast<int32_t *>(w + o_off),
+          *inc = reinterpret_cast<int32_t *>(w + o_inc);
+  HPMG_HIP(launch_traction_load(*op, coords, n_faces, face_elem, face_id, traction, rec, rnode, s));
+  // node -> face-record incidence lists, in record order (deterministic sums)
+  const int64_t nr = n_faces * op->P * op->P;
+  std::vector<int32_t> nodes(nr), hoff(op->N + 1, 0), hinc(nr);
+  HPMG_HIP(hipMemcpyAsync(nodes.data(), rnode, nr * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HPMG_HIP(hipStreamSynchronize(s));
+  for (int64_t k = 0; k < nr; ++k) {
+    if (nodes[k] < 0 || nodes[k] >= op->N) return fail(HPMG_ERR_SHAPE, "external_load: bad face element or face id");
+    hoff[nodes[k] + 1]++;
+  }
+  for (int64_t n = 0; n < op->N; ++n) hoff[n + 1] += hoff[n];
+  std::vector<int32_t> cur(hoff.begin(), hoff.end() - 1);
+  for (int64_t k = 0; k < nr; ++k) hinc[cur[nodes[k]]++] = (int32_t)k;
+  HPMG_HIP(hipMemcpyAsync(off, hoff.data(), hoff.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HPMG_HIP(hipMemcpyAsync(inc, hinc.data(), hinc.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HPMG_HIP(launch_assemble_csr(op->N, off, inc, rec, op->mask, tmp, s));
+  HPMG_HIP(launch_axpby(HPMG_F64, 3 * op->N, 1.0, tmp, 1.0, f_ext, s));
+  HPMG_HIP(hipStreamSynchronize(s));  // the host lists above must outlive the copies
+  return HPMG_OK;
+}
+
 int hpmg_state_initial_bytes(hpmg_op op, size_t *bytes) {
   if (!op || !bytes) return fail(HPMG_ERR_ARG, "state_initial_bytes: null argument");
   if (op->fine) return fail(HPMG_ERR_ARG, "state_initial_bytes: fine operators only");

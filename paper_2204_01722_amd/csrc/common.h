@@ -109,6 +109,12 @@ hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, double *uc, hipStream_t s);
 hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s);
+hipError_t launch_body_load(const hpmg_op_s &op, const double *g, double *f_ext, hipStream_t s);
+hipError_t launch_traction_load(const hpmg_op_s &op, const double *X, int64_t nf, const int32_t *face_elem,
+                                const int32_t *face_id, const double *t, double *rec, int32_t *rec_node,
+                                hipStream_t s);
+hipError_t launch_assemble_csr(int64_t N, const int32_t *off, const int32_t *inc, const double *rec,
+                               const uint8_t *mask, double *y, hipStream_t s);
 hipError_t launch_qdata(const hpmg_op_s &op, const double *coords, hipStream_t s);
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s);
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,

@@ -929,6 +929,98 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_state_initial(
 }
 
 // ------------------------------------------------------------------------------------
+// External dead loads (eq. variational-form, right-hand side).
+// Body force: per element int phi_a dV = sum_q B3[q][a] W_q, a transposed
+// interpolation of the point weights, times rho0 g; element records.
+// ------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(QT<Q>::NT) void k_body_load(const double *__restrict__ geo,
+                                                         const double *__restrict__ tab, double g0, double g1,
+                                                         double g2, double *__restrict__ ev, int64_t E) {
+  using T = double;
+  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
+  __shared__ T sB[Q * P];
+  __shared__ T lds[2 * ET * Q3];
+  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
+  const int64_t tile = xcd_tile();
+  const int64_t e = tile * ET + el;
+  const bool live = tq < NQ && e < E;
+  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
+  T *a = lds + (live ? el : 0) * Q3, *b = lds + ET * Q3 + (live ? el : 0) * Q3;
+  if (live) b[q] = geo[tile * NGEO * NQ + tq];  // W
+  __syncthreads();
+  interp_t<T, P, Q, 1>(b, a, sB, q, live);
+  if (live && q < P3) {
+    double *o = ev + ((int64_t)e * P3 + q) * 3;
+    const T v = a[q];
+    o[0] = v * g0;
+    o[1] = v * g1;
+    o[2] = v * g2;
+  }
+}
+
+// Traction on element faces, one thread per face: the face's P^2 nodes (local face
+// 0..5 = xi_1 = -1, +1, xi_2 = -1, +1, xi_3 = -1, +1), area element |X_,s x X_,r| from
+// the in-face derivatives at the Q^2 Gauss points, records [face][P^2][3] = int phi t dA
+// and the node of each record.
+template <int P, int Q>
+__global__ void k_traction_load(const double *__restrict__ X, const int32_t *__restrict__ elem_nodes,
+                                const int32_t *__restrict__ face_elem, const int32_t *__restrict__ face_id,
+                                const double *__restrict__ tab, double t0, double t1, double t2, int64_t nf,
+                                int64_t E, double *__restrict__ rec, int32_t *__restrict__ rec_node,
+                                unsigned *__restrict__ flags) {
+  const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const int32_t e = face_elem[f], id = face_id[f];
+  double *out = rec + f * P * P * 3;
+  int32_t *nodes = rec_node + f * P * P;
+  if (e < 0 || e >= E || id < 0 || id > 5) {  // reported to the host, nothing written
+    atomicOr(flags, 4u);
+    for (int k = 0; k < P * P; ++k) {
+      nodes[k] = -1;
+      out[3 * k] = out[3 * k + 1] = out[3 * k + 2] = 0.0;
+    }
+    return;
+  }
+  const int d = id / 2, ad = (id % 2) ? P - 1 : 0;
+  const int sd = d == 0 ? 1 : 0, rd = d == 2 ? 1 : 2;  // in-face directions, s < r
+  const int str[3] = {1, P, P * P};
+  double x[P * P][3];
+  for (int c = 0; c < P; ++c)
+    for (int b = 0; b < P; ++b) {
+      const int a = ad * str[d] + b * str[sd] + c * str[rd];
+      const int32_t n = elem_nodes[(int64_t)e * P * P * P + a];
+      nodes[b + P * c] = n;
+      for (int k = 0; k < 3; ++k) x[b + P * c][k] = X[(int64_t)n * 3 + k];
+    }
+  double acc[P * P];
+  for (int k = 0; k < P * P; ++k) acc[k] = 0.0;
+  const double *B = tab + TAB_B, *G = tab + TAB_G, *w = tab + TAB_W;
+  for (int j = 0; j < Q; ++j)
+    for (int i = 0; i < Q; ++i) {
+      double ts[3] = {0, 0, 0}, tr[3] = {0, 0, 0};
+      for (int c = 0; c < P; ++c)
+        for (int b = 0; b < P; ++b) {
+          const double gs = G[i * P + b] * B[j * P + c], gr = B[i * P + b] * G[j * P + c];
+          for (int k = 0; k < 3; ++k) {
+            ts[k] += gs * x[b + P * c][k];
+            tr[k] += gr * x[b + P * c][k];
+          }
+        }
+      const double n0 = ts[1] * tr[2] - ts[2] * tr[1], n1 = ts[2] * tr[0] - ts[0] * tr[2],
+                   n2 = ts[0] * tr[1] - ts[1] * tr[0];
+      const double dA = sqrt(n0 * n0 + n1 * n1 + n2 * n2) * w[i] * w[j];
+      for (int c = 0; c < P; ++c)
+        for (int b = 0; b < P; ++b) acc[b + P * c] += B[i * P + b] * B[j * P + c] * dA;
+    }
+  for (int k = 0; k < P * P; ++k) {
+    out[3 * k] = acc[k] * t0;
+    out[3 * k + 1] = acc[k] * t1;
+    out[3 * k + 2] = acc[k] * t2;
+  }
+}
+
+// ------------------------------------------------------------------------------------
 // a5': Jacobian action recomputing the linearisation from u and the geometry.
 // ------------------------------------------------------------------------------------
 template <typename T, int P, int Q>
@@ -1787,6 +1879,41 @@ hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipS
   HPMG_PQ_LIST(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_body_load(const hpmg_op_s &op, const double *g, double *f_ext, hipStream_t s) {
+#define X(p, q)                                                                                      \
+  if (op.P == p && op.Q == q) {                                                                      \
+    k_body_load<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.geo, op.tab64, g[0], g[1], g[2], op.evec, \
+                                                               op.E);                                \
+    hipError_t e = hipGetLastError();                                                                \
+    return e != hipSuccess ? e : assemble<double>(op, nullptr, f_ext, s);                            \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_traction_load(const hpmg_op_s &op, const double *coords, int64_t nf, const int32_t *face_elem,
+                                const int32_t *face_id, const double *t, double *rec, int32_t *rec_node,
+                                hipStream_t s) {
+#define X(p, q)                                                                                      \
+  if (op.P == p && op.Q == q) {                                                                      \
+    k_traction_load<p, q><<<grid1d(nf, 64), 64, 0, s>>>(coords, op.elem_nodes, face_elem, face_id,        \
+                                                         op.tab64,                                    \
+                                                         t[0], t[1], t[2], nf, op.E, rec, rec_node,   \
+                                                         op.flags);                                  \
+    return hipGetLastError();                                                                        \
+  }
+  HPMG_PQ_LIST(X)
+#undef X
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_assemble_csr(int64_t N, const int32_t *off, const int32_t *inc, const double *rec,
+                               const uint8_t *mask, double *y, hipStream_t s) {
+  k_assemble<double><<<grid1d(N, 256), 256, 0, s>>>(N, off, inc, rec, mask, nullptr, 0.0, y);
+  return hipGetLastError();
 }
 
 hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s) {

@@ -612,9 +612,9 @@ static int store_state(hpmg_op fine, hpmg_mg_s *mg, const double *u, hipStream_t
 // accepted point is checked for inverted elements and non-finite values; the step is
 // halved (at most 6 times) until it passes.  Returns HPMG_OK on convergence, else an
 // error that tells the caller to cut the increment.
-static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_newton_params *prm,
-                          const double *const *seeds, void *stream, double load, int *its_out, int *lin_out,
-                          double *rel_out) {
+static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *f_ext,
+                          const hpmg_newton_params *prm, const double *const *seeds, void *stream, double load,
+                          int *its_out, int *lin_out, double *rel_out) {
   int st;
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
@@ -622,6 +622,7 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
   *its_out = 0;
   *rel_out = 0.0;
   HPMG_HIP(launch_residual(*fine, u, F, false, s));
+  if (f_ext) HPMG_HIP(launch_axpby(HPMG_F64, n, -load, f_ext, 1.0, F, s));
   HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
   if ((st = read_scalars(mg, 1, s))) return st;
   const double f0 = std::sqrt(mg->host[0]);
@@ -654,6 +655,7 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
       // g(a) = F(u + a du)^T du; one secant step from a = 0 and a = 1.
       HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 1.0, du, ut, s));
       HPMG_HIP(launch_residual(*fine, ut, mg->fq, false, s));
+      if (f_ext) HPMG_HIP(launch_axpby(HPMG_F64, n, -load, f_ext, 1.0, mg->fq, s));
       HPMG_HIP(launch_dot(HPMG_F64, n, mg->fq, du, mg->red, mg->scal, s));
       if ((st = read_scalars(mg, 1, s))) return st;
       const double g1 = mg->host[0];
@@ -673,6 +675,7 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
       fine->state_version++;
       fine->state_ready = true;
       fine->state32_ready = false;
+      if (f_ext) HPMG_HIP(launch_axpby(HPMG_F64, n, -load, f_ext, 1.0, F, s));
       HPMG_HIP(launch_dot(HPMG_F64, n, F, F, mg->red, mg->scal, s));
       if ((st = read_scalars(mg, 1, s))) return st;
       fn = std::sqrt(mg->host[0]);
@@ -695,7 +698,7 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const hpmg_new
   return HPMG_OK;
 }
 
-int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext, int n_steps,
                       const hpmg_newton_params *prm, const double *const *seeds, double *stats, void *stream) {
   int st = mg_check(mg, "newton_solve");
   if (st) return st;
@@ -730,7 +733,8 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, i
       HPMG_HIP(launch_axpby(HPMG_F64, n, inc / n_steps, lift, 1.0, u, s));
       int its = 0;
       double rel = 0.0;
-      st = newton_at_load(fine, mg, u, prm, seeds, stream, (step + done + inc) / n_steps, &its, &total_lin, &rel);
+      st = newton_at_load(fine, mg, u, f_ext, prm, seeds, stream, (step + done + inc) / n_steps, &its, &total_lin,
+                          &rel);
       if (st && prm->monitor)
         std::fprintf(stderr, "[newton] load %.6f failed (%s); halving the increment\n", (step + done + inc) / n_steps,
                      hpmg_last_error());
@@ -793,7 +797,7 @@ int hpmg_lbfgs_workspace_bytes(hpmg_mg mg, int memory, size_t *bytes) {
   return HPMG_OK;
 }
 
-int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, int n_steps,
+int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext, int n_steps,
                      const hpmg_lbfgs_params *prm, const double *const *seeds, void *workspace,
                      size_t workspace_bytes, double *stats, void *stream) {
   int st = mg_check(mg, "lbfgs_solve");
@@ -828,8 +832,10 @@ int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, in
     *out = mg->host[0];
     return HPMG_OK;
   };
+  double load = 0.0;  // fraction of the external load in the current step
   auto gradient = [&](const double *x, double *out, bool store, double *norm, unsigned *flags) -> int {
     HPMG_HIP(launch_residual(*fine, x, out, store, s));
+    if (f_ext) HPMG_HIP(launch_axpby(HPMG_F64, n, -load, f_ext, 1.0, out, s));
     if (store) {
       fine->state_version++;
       fine->state_ready = true;
@@ -846,6 +852,7 @@ int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, in
   double final_rel = 0.0;
   std::vector<double> rho(m), alph(m);
   for (int step = 0; step < n_steps; ++step) {
+    load = (double)(step + 1) / n_steps;
     HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0 / n_steps, lift, 1.0, u, s));
     // The V-cycle is built once per load step, on the tangent at the lifted start.
     double gn = 0.0;

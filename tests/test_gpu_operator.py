@@ -291,3 +291,28 @@ def test_element_matrices_go_stale_with_the_state():
     Kc = fem.apply_bc(Ks[1], H.masks[1])
     x = inputs.random_vector(H.ops[1].n_nodes, 41)
     assert rel(t2n(H.ops[1].jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_external_load_matches_oracle(p):
+    """Body force and traction dead loads (Q2, Q4 on a 2 x 1 x 0.5 box, jittered,
+    constrained x = 0 face) against the oracle's quadrature of their definitions."""
+    print_case("external_load", p=p)
+    L = (2.0, 1.0, 0.5)
+    faces_bc = {"x0": (1, 1, 1)}
+    m = inputs.box_mesh(2, p, L=L, jitter=0.08)
+    from paper_2204_01722_amd.problem import Hierarchy
+    H = Hierarchy(m, [p], faces=faces_bc)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    g = np.array([0.3, -1.2, 0.7])
+    t = np.array([0.25, 0.5, -1.0])
+    loaded = [(1 + 2 * (ey + 2 * ez), 1) for ez in range(2) for ey in range(2)]
+    mask = inputs.face_mask(m, faces_bc).astype(bool)
+    ref = fem.body_force_load(d, g) + fem.traction_load(m.coords, m.elem_nodes, m.P, m.P, loaded, t)
+    ref[mask] = 0.0
+    f = H.fine.external_load(g, H.coords, loaded, t)
+    assert rel(t2n(f), ref) < TOL64
+    fb = H.fine.external_load(g)
+    refb = fem.body_force_load(d, g)
+    refb[mask] = 0.0
+    assert rel(t2n(fb), refb) < TOL64

@@ -368,3 +368,35 @@ def test_newton_with_rediscretised_levels():
     u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
     u, st = PMG(H.ops, precision="f32").lbfgs(u, _dev(lift_np), 2, H.seeds(7), rtol=1e-10)
     assert rel(t2n(u), ref) < 1e-8
+
+
+def test_newton_uniaxial_stress_by_traction():
+    """Roller faces x = 0, y = 0, z = 0, traction T on x = 1 in three load steps: the
+    GPU Newton and L-BFGS solves reach the homogeneous uniaxial-stress state
+    (closed form)."""
+    import torch
+    from scipy.optimize import fsolve
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("newton_traction")
+    T = 0.12
+    faces = {"x0": (1, 0, 0), "y0": (0, 1, 0), "z0": (0, 0, 1)}
+    m = inputs.box_mesh(2, 2, jitter=0.08)
+    H = Hierarchy(m, [2, 1], faces=faces)
+    loaded = [(1 + 2 * (ey + 2 * ez), 1) for ez in range(2) for ey in range(2)]
+    f_ext = H.fine.external_load(None, H.coords, loaded, (T, 0.0, 0.0))
+
+    def eqs(x):
+        l1, l2 = x
+        lj = np.log(l1 * l2 * l2)
+        return [MU * (l1 - 1 / l1) + LAM * lj / l1 - T, MU * (l2 - 1 / l2) + LAM * lj / l2]
+    l1, l2 = fsolve(eqs, [1.1, 0.97], xtol=1e-13)
+    exact = m.coords * np.array([l1 - 1.0, l2 - 1.0, l2 - 1.0])
+    zero = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    u = zero.clone()
+    u, st = PMG(H.ops, precision="f64").newton(u, zero, 3, H.seeds(7), rtol=1e-11, lin_rtol=1e-8, f_ext=f_ext)
+    print(f"[newton_traction] stats={st}", flush=True)
+    assert np.abs(t2n(u) - exact).max() < 1e-9
+    u = zero.clone()
+    u, st = PMG(H.ops, precision="f32").lbfgs(u, zero, 3, H.seeds(7), rtol=1e-11, f_ext=f_ext)
+    assert np.abs(t2n(u) - exact).max() < 1e-9
