@@ -109,6 +109,31 @@ class Workload:
         return lambda: self.op.residual(self.u, store_state=True, out=self.r)
 
 
+def adjoint_bench(steps, warmup, stream):
+    """The differentiation workload: Q3 on a 23^3 jittered box (1,029,000 DoF), per-element
+    Lame parameters log-uniform on [0.5, 2]; times of the adjoint (VJP) kernel giving
+    u_bar, mu_bar and lambda_bar, FP64 and FP32, stored and recomputed linearisation."""
+    import torch
+    from paper_2204_01722_amd import inputs
+    from paper_2204_01722_amd.problem import Hierarchy
+    m = inputs.box_mesh(23, 3, jitter=0.05, seed=2204)
+    mu_e, lam_e = inputs.loguniform_materials(m.n_elem, seed=4)
+    H = Hierarchy(m, [3], faces={"x0": (1, 1, 1)}, mu_e=mu_e, lam_e=lam_e)
+    op = H.fine
+    u = torch.from_numpy(inputs.config1_u(m, amplitude=0.05)).cuda()
+    w = torch.from_numpy(inputs.random_vector(m.n_nodes, 5)).cuda()
+    w32 = w.float()
+    op.residual(u, store_state=True)
+    op.state_cast_f32()
+    out = {"workload": "Q3 on a 23^3 jittered box, 1,029,000 DoF, per-element Lame parameters log-uniform "
+                       "on [0.5, 2]; one VJP = u_bar, mu_bar, lambda_bar", "dof": 3 * m.n_nodes}
+    for prec, ww in (("f64", w), ("f32", w32)):
+        for mode in ("stored", "recompute"):
+            t = time_op(lambda: op.residual_vjp(u, ww, mode=mode, precision=prec), steps, warmup, stream)
+            out[f"{prec}_{mode}"] = {"ms": t, "GDoF/s": 3 * m.n_nodes / (t * 1e-3) / 1e9}
+    return out
+
+
 def cpu_baseline(wl, target_s=15.0):
     """The oracle's matrix-free Jacobian apply (dense element tables, FP64, numpy) on a
     bounded sample of the workload's elements; rate scaled to DoF of the full mesh."""
@@ -303,6 +328,8 @@ def main():
                     (t * 1e-3) / 1e9 / HBM_PEAK_GBPS}
             del wl
             torch.cuda.empty_cache()
+        print("[bench] adjoint (Q3 23^3)", file=sys.stderr, flush=True)
+        variants["adjoint_q3_23cubed"] = adjoint_bench(max(5, args.steps // 5), 2, stream)
         print(f"[bench] variants done", file=sys.stderr, flush=True)
     # a plain device copy of known size: achievable bandwidth, and the reference kernel
     # that scales the HBM byte counters of a profiled run

@@ -208,9 +208,11 @@ int hpmg_energy(hpmg_op op, const double *u, double *psi, void *stream);
  *   u_bar = (dr/du)^T w, written as the transposed pointwise map (adjoint kernel),
  *   mu_bar[e] = dr/dmu_e^T w, lambda_bar[e] = dr/dlambda_e^T w  (per element).
  * mode HPMG_STORED uses the linearisation stored by the last hpmg_residual at this u
- * (parameter gradients then need mu_e, lambda_e > 0); HPMG_RECOMPUTE rebuilds it
- * from u.  mu_bar / lambda_bar may be NULL.  All double. */
-int hpmg_residual_vjp(hpmg_op op, int mode, const double *u, const double *w, double *u_bar,
+ * (parameter gradients then need mu_e, lambda_e > 0; FP32 needs hpmg_state_cast_f32);
+ * HPMG_RECOMPUTE rebuilds it from u (double).  precision HPMG_F64: w, u_bar double;
+ * HPMG_F32: w, u_bar float, FP32 arithmetic (J - 1 and log J in double).  mu_bar /
+ * lambda_bar (double [n_elem]) may be NULL. */
+int hpmg_residual_vjp(hpmg_op op, int precision, int mode, const double *u, const void *w, void *u_bar,
                       double *mu_bar, double *lambda_bar, void *stream);
 
 /* ---------------------------------------------------------------------------------

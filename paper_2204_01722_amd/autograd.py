@@ -14,20 +14,24 @@ from .binding import Operator
 
 
 class NeoHookeanResidual(torch.autograd.Function):
-    """``r = NeoHookeanResidual.apply(u, mu_e, lam_e, op, mode)``.
+    """``r = NeoHookeanResidual.apply(u, mu_e, lam_e, op, mode, precision)``.
 
     ``u``: float64 [n_nodes][3] on the device; ``mu_e``, ``lam_e``: float64 [n_elem];
     ``op``: the fine :class:`Operator` (its geometry set up); ``mode``: "stored" or
-    "recompute" (how the backward obtains the linearisation)."""
+    "recompute" (how the backward obtains the linearisation); ``precision``: "f64" or
+    "f32" arithmetic of the backward (the forward residual is FP64; the gradients are
+    returned as float64)."""
 
     @staticmethod
-    def forward(ctx, u, mu_e, lam_e, op: Operator, mode: str = "recompute"):
+    def forward(ctx, u, mu_e, lam_e, op: Operator, mode: str = "recompute", precision: str = "f64"):
         mu_e = mu_e.detach().contiguous()
         lam_e = lam_e.detach().contiguous()
         op.set_material(0.0, 0.0, mu_e, lam_e)
         ud = u.detach().contiguous()
         r = op.residual(ud, store_state=(mode == "stored"))
-        ctx.op, ctx.mode = op, mode
+        if mode == "stored" and precision == "f32":
+            op.state_cast_f32()
+        ctx.op, ctx.mode, ctx.precision = op, mode, precision
         ctx.save_for_backward(ud, mu_e, lam_e)
         return r
 
@@ -36,5 +40,6 @@ class NeoHookeanResidual(torch.autograd.Function):
         u, mu_e, lam_e = ctx.saved_tensors
         op = ctx.op
         op.set_material(0.0, 0.0, mu_e, lam_e)
-        ub, mub, lamb = op.residual_vjp(u, r_bar.contiguous().to(torch.float64), mode=ctx.mode)
-        return ub, mub, lamb, None, None
+        wt = torch.float64 if ctx.precision == "f64" else torch.float32
+        ub, mub, lamb = op.residual_vjp(u, r_bar.contiguous().to(wt), mode=ctx.mode, precision=ctx.precision)
+        return ub.to(torch.float64), mub, lamb, None, None, None

@@ -74,7 +74,7 @@ _SIGS = {
     "hpmg_prolong_add": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
     "hpmg_restrict": ([_VP, _VP, _I, _VP, _VP, _VP], _I),
     "hpmg_energy": ([_VP, _VP, _VP, _VP], _I),
-    "hpmg_residual_vjp": ([_VP, _I, _VP, _VP, _VP, _VP, _VP, _VP], _I),
+    "hpmg_residual_vjp": ([_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP], _I),
     "hpmg_vec_dot": ([_I, _I64, _VP, _VP, _VP, _VP, _VP], _I),
     "hpmg_vec_axpby": ([_I, _I64, _D, _VP, _D, _VP, _VP], _I),
     "hpmg_vec_cast": ([_I64, _I, _VP, _VP, _VP], _I),
@@ -335,15 +335,16 @@ class Operator:
         _check(lib().hpmg_energy(self.h, _p(u), _p(psi), _stream()))
         return psi
 
-    def residual_vjp(self, u, w, mode="recompute", want_params=True):
+    def residual_vjp(self, u, w, mode="recompute", want_params=True, precision="f64"):
+        prec = _prec(precision)
         u = self._in(u)
-        w = self._in(w)
-        ub = self._vec()
+        w = self._in(w, _dtype(prec))
+        ub = self._vec(_dtype(prec))
         mub = lamb = None
         if want_params:
             mub = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
             lamb = torch.empty(self.n_elem, dtype=torch.float64, device=self.device)
-        _check(lib().hpmg_residual_vjp(self.h, _mode(mode), _p(u), _p(w), _p(ub), _p(mub), _p(lamb),
+        _check(lib().hpmg_residual_vjp(self.h, prec, _mode(mode), _p(u), _p(w), _p(ub), _p(mub), _p(lamb),
                                        _stream()))
         return ub, mub, lamb
 

@@ -508,20 +508,23 @@ int hpmg_energy(hpmg_op op, const double *u, double *psi, void *stream) {
   return HPMG_OK;
 }
 
-int hpmg_residual_vjp(hpmg_op op, int mode, const double *u, const double *w, double *u_bar, double *mu_bar,
-                      double *lambda_bar, void *stream) {
+int hpmg_residual_vjp(hpmg_op op, int precision, int mode, const double *u, const void *w, void *u_bar,
+                      double *mu_bar, double *lambda_bar, void *stream) {
   int st = check_ready(op, "residual_vjp");
   if (st) return st;
+  if ((st = check_prec(precision, "residual_vjp"))) return st;
   if (op->fine || !op->geo_ready) return fail(HPMG_ERR_ARG, "residual_vjp: needs a fine operator with geometry");
   if (!w || !u_bar) return fail(HPMG_ERR_ARG, "residual_vjp: null vector");
   if (mode == HPMG_STORED) {
     if (!op->state_ready) return fail(HPMG_ERR_ARG, "residual_vjp: no stored linearisation");
+    if (precision == HPMG_F32 && !op->state32_ready)
+      return fail(HPMG_ERR_ARG, "residual_vjp: FP32 state not cast (hpmg_state_cast_f32)");
   } else if (mode == HPMG_RECOMPUTE) {
     if (!u) return fail(HPMG_ERR_ARG, "residual_vjp: recompute mode needs u");
   } else {
     return fail(HPMG_ERR_ARG, "residual_vjp: bad mode");
   }
-  HPMG_HIP(launch_vjp(*op, mode, u, w, u_bar, mu_bar, lambda_bar, S(stream)));
+  HPMG_HIP(launch_vjp(*op, precision, mode, u, w, u_bar, mu_bar, lambda_bar, S(stream)));
   return HPMG_OK;
 }
 

@@ -125,7 +125,7 @@ hipError_t launch_prolong_add(const hpmg_op_s &coarse, const hpmg_op_s &fine, in
 hipError_t launch_restrict(const hpmg_op_s &fine, const hpmg_op_s &coarse, int prec, const void *rf,
                            void *rc, hipStream_t s);
 hipError_t launch_energy(const hpmg_op_s &op, const double *u, double *psi, hipStream_t s);
-hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
+hipError_t launch_vjp(const hpmg_op_s &op, int prec, int mode, const double *u, const void *w, void *ub,
                       double *mub, double *lamb, hipStream_t s);
 hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s);
 hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s);

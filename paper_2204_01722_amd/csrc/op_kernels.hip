@@ -1427,13 +1427,12 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_energy(const uint32_t *__restrict
 // ------------------------------------------------------------------------------------
 // a16: adjoint (vector-Jacobian product) of the masked residual.
 // ------------------------------------------------------------------------------------
-template <int P, int Q, bool STORED>
+template <typename T, int P, int Q, bool STORED>
 __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
-    const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ w,
-    const double *__restrict__ geo, const double *__restrict__ state, const double *__restrict__ tab,
+    const uint32_t *__restrict__ emap, const double *__restrict__ u, const T *__restrict__ w,
+    const double *__restrict__ geo, const T *__restrict__ state, const T *__restrict__ tab,
     double mu0, double lam0, const double *__restrict__ mu_e, const double *__restrict__ lam_e,
-    double *__restrict__ ev, double *__restrict__ mub, double *__restrict__ lamb, int64_t E) {
-  using T = double;
+    T *__restrict__ ev, double *__restrict__ mub, double *__restrict__ lamb, int64_t E) {
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int NC = STORED ? 3 : 6;
   constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
@@ -1451,8 +1450,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
     const uint32_t node = wd & EMAP_ID_MASK;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      a[c * P3 + q] = ((wd >> (EMAP_BC_SHIFT + c)) & 1u) ? 0.0 : w[(int64_t)node * 3 + c];
-      if (!STORED) a[(3 + c) * P3 + q] = u[(int64_t)node * 3 + c];
+      a[c * P3 + q] = ((wd >> (EMAP_BC_SHIFT + c)) & 1u) ? T(0) : w[(int64_t)node * 3 + c];
+      if (!STORED) a[(3 + c) * P3 + q] = (T)u[(int64_t)node * 3 + c];
     }
   }
   __syncthreads();
@@ -1465,7 +1464,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int k = 0; k < 3; ++k) C[i][k] = G[i][k];
-    const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
+    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
     T twoe[6];
     double logJ;
     if (STORED) {
@@ -1480,8 +1479,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
       W = s[16 * NQ];
       // tau = 2 mu e + c I and c = lambda log J
 #pragma unroll
-      for (int m = 0; m < 6; ++m) twoe[m] = (tau[m] - (m < 3 ? c : 0.0)) / mu;
-      logJ = c / lam;
+      for (int m = 0; m < 6; ++m) twoe[m] = (tau[m] - (m < 3 ? c : T(0))) / mu;
+      logJ = (double)c / (double)lam;
     } else {
       T Gu[3][3], D[3][3];
 #pragma unroll
@@ -1489,11 +1488,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
 #pragma unroll
         for (int k = 0; k < 3; ++k) Gu[i][k] = G[NC - 3 + i][k];
       const double *g = geo + tile * NGEO * NQ + tq;
-      W = g[0];
+      W = (T)g[0];
 #pragma unroll
       for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int J = 0; J < 3; ++J) D[k][J] = g[(1 + k * 3 + J) * NQ];
+        for (int J = 0; J < 3; ++J) D[k][J] = (T)g[(1 + k * 3 + J) * NQ];
       Kin<T> k;
       kinematics(Gu, D, mu, lam, k);
 #pragma unroll
@@ -1519,7 +1518,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) d += M[i][j] * twoe[sym_index(i, j)];
     pm = W * d;
-    pl = W * logJ * (M[0][0] + M[1][1] + M[2][2]);
+    pl = W * (T)logJ * (M[0][0] + M[1][1] + M[2][2]);
   }
   __syncthreads();
   // per-element parameter gradients: stage the point values in b, sum serially
@@ -1535,8 +1534,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
       sm += b[i];
       sl += b[Q3 + i];
     }
-    if (mub) mub[e] = sm;
-    if (lamb) lamb[e] = sl;
+    if (mub) mub[e] = (double)sm;
+    if (lamb) lamb[e] = (double)sl;
   }
   // move the transposed-gradient result to the front of b for interp_t
   T tmp[3];
@@ -1929,29 +1928,38 @@ hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_vjp(const hpmg_op_s &op, int mode, const double *u, const double *w, double *ub,
-                      double *mub, double *lamb, hipStream_t s) {
-  double *ev = op.evec;
+template <typename T>
+static hipError_t vjp_t(const hpmg_op_s &op, int mode, const double *u, const T *w, T *ub, double *mub,
+                        double *lamb, hipStream_t s) {
+  T *ev = (T *)op.evec;
+  const T *state = std::is_same<T, double>::value ? (const T *)op.state64 : (const T *)op.state32;
+  const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
 #define X(p, q)                                                                                      \
   if (op.P == p && op.Q == q) {                                                                      \
     if (mode == HPMG_STORED)                                                                         \
-      k_vjp<p, q, true><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,   \
-                                                                 op.tab64, op.mu, op.lam, op.mu_e,   \
-                                                                 op.lam_e, ev, mub, lamb, op.E);     \
+      k_vjp<T, p, q, true><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, state, tab,  \
+                                                                    op.mu, op.lam, op.mu_e, op.lam_e, \
+                                                                    ev, mub, lamb, op.E);            \
     else                                                                                             \
-      k_vjp<p, q, false><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, op.state64,  \
-                                                                  op.tab64, op.mu, op.lam, op.mu_e,  \
-                                                                  op.lam_e, ev, mub, lamb, op.E);    \
+      k_vjp<T, p, q, false><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, w, op.geo, state, tab, \
+                                                                     op.mu, op.lam, op.mu_e, op.lam_e, \
+                                                                     ev, mub, lamb, op.E);           \
     hipError_t e = hipGetLastError();                                                                \
     if (e != hipSuccess) return e;                                                                   \
     /* unmasked assembly: constrained columns of u_bar are kept */                                   \
-    k_assemble<double><<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, ev, nullptr,   \
-                                                         nullptr, 0.0, ub);                          \
+    k_assemble<T><<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, ev, nullptr, nullptr, \
+                                                    T(0), ub);                                       \
     return hipGetLastError();                                                                        \
   }
   HPMG_PQ_LIST(X)
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_vjp(const hpmg_op_s &op, int prec, int mode, const double *u, const void *w, void *ub,
+                      double *mub, double *lamb, hipStream_t s) {
+  if (prec == HPMG_F64) return vjp_t<double>(op, mode, u, (const double *)w, (double *)ub, mub, lamb, s);
+  return vjp_t<float>(op, mode, u, (const float *)w, (float *)ub, mub, lamb, s);
 }
 
 hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s) {

@@ -243,6 +243,14 @@ def test_vjp(mode):
     assert rel(t2n(ub), ub_ref) < TOL64
     assert rel(t2n(mub), mub_ref) < TOL64
     assert rel(t2n(lamb), lamb_ref) < TOL64
+    # FP32 arithmetic (FP32 state in stored mode)
+    H.fine.state_cast_f32()
+    import torch
+    ub, mub, lamb = H.fine.residual_vjp(_dev(u), _dev(w).float(), mode=mode, precision="f32")
+    assert ub.dtype == torch.float32
+    assert rel(t2n(ub), ub_ref) < TOL32
+    assert rel(t2n(mub), mub_ref) < TOL32
+    assert rel(t2n(lamb), lamb_ref) < TOL32
 
 
 @pytest.mark.parametrize("n,p", [(43, 2), (34, 4)])

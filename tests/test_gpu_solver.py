@@ -173,6 +173,16 @@ def test_autograd_residual():
         assert rel(t2n(ut.grad), ub) < 1e-12, mode
         assert rel(t2n(mt.grad), mub) < 1e-12, mode
         assert rel(t2n(lt.grad), lamb) < 1e-12, mode
+        # the FP32 backward
+        ut = _dev(u2).requires_grad_(True)
+        mt = _dev(mu_e2).requires_grad_(True)
+        lt = _dev(lam_e2).requires_grad_(True)
+        r = NeoHookeanResidual.apply(ut, mt, lt, H2.fine, mode, "f32")
+        (r * _dev(w2)).sum().backward()
+        assert ut.grad.dtype == torch.float64
+        assert rel(t2n(ut.grad), ub) < 1e-5, mode
+        assert rel(t2n(mt.grad), mub) < 1e-5, mode
+        assert rel(t2n(lt.grad), lamb) < 1e-5, mode
 
 
 def test_adjoint_full_size_sampled():
