@@ -107,6 +107,15 @@ int ctof_table(int Pf, int Pc, double *M);
 bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
+// Stored-mode apply whose assembly also writes per-workgroup partials of du . y
+// (ceil(N / 256) of them, in pq); the atomic scatter mode is not supported.
+hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
+                               hipStream_t s);
+hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
+                              const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
+                              double *partial, hipStream_t s);
+hipError_t launch_pcg_dir2(int prec, int64_t n, double *sc, int parity, const double *partial, const void *z,
+                           void *p, hipStream_t s);
 hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, double *uc, hipStream_t s);
 hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s);
 hipError_t launch_body_load(const hpmg_op_s &op, const double *g, double *f_ext, hipStream_t s);

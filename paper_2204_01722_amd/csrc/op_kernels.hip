@@ -1624,6 +1624,43 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__re
   }
 }
 
+// The same assembly fused with the partial dot product p . y of the assembled result
+// and the direction p (= src), one partial per workgroup (fixed tree): the Jacobi-PCG
+// step needs p^T A p right after A p.
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble_dot(int64_t N, const int32_t *__restrict__ off,
+                                                      const int32_t *__restrict__ inc, const T *__restrict__ ev,
+                                                      const uint8_t *__restrict__ mask, const T *__restrict__ src,
+                                                      T *__restrict__ y, double *__restrict__ partial) {
+  __shared__ double red[256];
+  const int64_t tile = xcd_tile();
+  const int64_t n = tile * blockDim.x + threadIdx.x;
+  double pq = 0.0;
+  if (n < N) {
+    const int32_t k0 = off[n], k1 = off[n + 1];
+    T a[3] = {0, 0, 0};
+    for (int32_t k = k0; k < k1; ++k) {
+      const T *p = ev + (int64_t)inc[k] * 3;
+      a[0] += p[0];
+      a[1] += p[1];
+      a[2] += p[2];
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (mask && mask[n * 3 + c]) a[c] = src[n * 3 + c];
+      y[n * 3 + c] = a[c];
+      pq += (double)src[n * 3 + c] * (double)a[c];
+    }
+  }
+  red[threadIdx.x] = pq;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < (unsigned)w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[tile] = red[0];
+}
+
 inline unsigned grid1d(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 // y = assembled element records of `op`; constrained components take src (or `fill`).
@@ -1769,7 +1806,17 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
 }
 
 template <typename T>
-static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, const T *du, T *y, hipStream_t s) {
+static hipError_t assemble_or_dot(const hpmg_op_s &op, const T *du, T *y, double *pq, hipStream_t s) {
+  if (!pq) return assemble<T>(op, du, y, s);
+  k_assemble_dot<T><<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask,
+                                                      du, y, pq);
+  return hipGetLastError();
+}
+
+// pq != NULL: the assembly also writes per-workgroup partials of du . y (ceil(N / 256)).
+template <typename T>
+static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, const T *du, T *y, hipStream_t s,
+                             double *pq = nullptr) {
   const hpmg_op_s &f = op.fine ? *op.fine : op;
   const bool atom = use_atomic_scatter();
   if (atom) {
@@ -1783,7 +1830,7 @@ static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, con
     k_elmat_apply<T><<<grid1d(op.E, ELB), ELB * 24, 0, s>>>(op.emap, (const T *)op.elmat, du, ev, op.E);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
-    return assemble<T>(op, du, y, s);
+    return assemble_or_dot<T>(op, du, y, pq, s);
   }
   hipError_t e = hipErrorInvalidValue;
 #define X(p, q) \
@@ -1791,7 +1838,14 @@ static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, con
   HPMG_PQ_LIST(X)
 #undef X
   if (e != hipSuccess || atom) return e;
-  return assemble<T>(op, du, y, s);
+  return assemble_or_dot<T>(op, du, y, pq, s);
+}
+
+hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
+                               hipStream_t s) {
+  if (use_atomic_scatter()) return hipErrorInvalidValue;
+  if (prec == HPMG_F64) return jacobian_t<double>(op, HPMG_STORED, nullptr, (const double *)du, (double *)y, s, pq);
+  return jacobian_t<float>(op, HPMG_STORED, nullptr, (const float *)du, (float *)y, s, pq);
 }
 
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,

@@ -38,6 +38,7 @@ struct hpmg_mg_s {
   char *ws = nullptr;
   size_t bytes = 0;
   double *red = nullptr;     // reduction partials
+  double *pq_part = nullptr; // per-workgroup partials of p.q from the coarse fused assembly
   double *scal = nullptr;    // device scalars (8)
   double *host = nullptr;    // pinned host mirror (8)
   // fine FP64 vectors for the Krylov and Newton drivers
@@ -65,6 +66,7 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   };
   mg->red = reinterpret_cast<double *>(take(2 * RED_BLOCKS * sizeof(double) * 2));
   mg->scal = reinterpret_cast<double *>(take(16 * sizeof(double)));
+  mg->pq_part = reinterpret_cast<double *>(take((size_t)((mg->lv.back().n / 3 + 255) / 256 + 1) * sizeof(double)));
   for (Level &L : mg->lv) {
     const size_t nb = (size_t)L.n * es;
     L.b = take(nb);
@@ -152,24 +154,30 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
   HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, 0.0, L.b, L.r, s));
   HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, sc + 2, s));  // sc[2] = rz, sc[3] = rr
   HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.z, 0.0, L.z, L.d, s));
-  HPMG_HIP(hipMemcpyAsync(sc, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));  // sc[0] = rz
+  HPMG_HIP(hipMemcpyAsync(sc + 8, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));  // sc[8] = rz
   HPMG_HIP(launch_set_scalar(sc, 5, 0.0, s));
   if ((st = read_scalars(mg, 4, s))) return st;
   const double bn = std::sqrt(mg->host[3]);
   *its_out = 0;
   if (fixed <= 0 && bn == 0.0) return HPMG_OK;
   const int limit = fixed > 0 ? fixed : maxit;
+  const int nb_pq = (int)((L.n / 3 + 255) / 256);
   int its = 0;
+  // Four launches per iteration: element kernel, assembly fused with p.Ap, the update
+  // (alpha from the p.Ap partials) and the direction (beta from the r.z partials).
   while (its < limit) {
-    if ((st = apply(mg, L, prec, L.d, L.t, s))) return st;
-    HPMG_HIP(launch_dot(prec, L.n, L.d, L.t, mg->red, sc + 1, s));
-    HPMG_HIP(launch_pcg_update(prec, L.n, sc, L.d, L.t, L.x, L.r, L.dinv, L.z, mg->red, s));
+    HPMG_HIP(launch_jacobian_dot(*L.op, prec, L.d, L.t, mg->pq_part, s));
+    const size_t l = &L - mg->lv.data();
+    if (l < 8) mg->n_applies[l]++;
+    const int parity = its & 1;
+    HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, L.x, L.r, L.dinv, L.z,
+                                mg->red, s));
+    HPMG_HIP(launch_pcg_dir2(prec, L.n, sc, parity, mg->red, L.z, L.d, s));
     ++its;
     if (fixed <= 0 && (its % check == 0 || its == limit)) {
       if ((st = read_scalars(mg, 6, s))) return st;
       if (mg->host[5] != 0.0 || std::sqrt(mg->host[3]) <= rtol * bn) break;
     }
-    HPMG_HIP(launch_pcg_dir(prec, L.n, sc, L.z, L.d, s));
   }
   *its_out = its;
   return HPMG_OK;

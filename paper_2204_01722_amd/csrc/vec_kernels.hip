@@ -253,6 +253,70 @@ __global__ __launch_bounds__(BS) void k_pcg_dir(int64_t n, const double *__restr
   GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
 }
 
+// Sum of partial[0 .. nb) in a fixed order, identical in every workgroup (each thread
+// adds a strided subset in order, then a fixed tree).
+__device__ __forceinline__ double block_reduce_fixed(const double *__restrict__ partial, int nb) {
+  __shared__ double s[BS];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS) t += partial[i];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = BS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Fused Jacobi-PCG steps for the coarse solve.  The search direction's curvature p.q
+// arrives as workgroup partials of the fused assembly; rz alternates between scalar
+// slots 8 and 9 so that no workgroup overwrites a value another one still reads.
+// update2: alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z, r.r.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restrict__ sc, int parity, int nb_pq,
+                                                    const double *__restrict__ pq_partial,
+                                                    const T *__restrict__ p, const T *__restrict__ q,
+                                                    T *__restrict__ x, T *__restrict__ r,
+                                                    const T *__restrict__ dinv, T *__restrict__ z,
+                                                    double *__restrict__ partial) {
+  const double pq = block_reduce_fixed(pq_partial, nb_pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[1] = pq;
+    if (!(pq > 0.0)) sc[5] = 1.0;
+  }
+  const T a = (T)(pq > 0.0 ? sc[8 + parity] / pq : 0.0);
+  double v[2] = {0.0, 0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    const T zi = dinv[i] * ri;
+    z[i] = zi;
+    v[0] += (double)ri * (double)zi;
+    v[1] += (double)ri * (double)ri;
+  }
+  block_store<2>(v, partial);
+}
+
+// dir2: rz_new and r.r from the partials, beta = rz_new / rz, p = z + beta p.
+template <typename T>
+__global__ __launch_bounds__(BS) void k_pcg_dir2(int64_t n, double *__restrict__ sc, int parity,
+                                                 const double *__restrict__ partial, const T *__restrict__ z,
+                                                 T *__restrict__ p) {
+  const double rz_new = block_reduce_fixed(partial, RED_BLOCKS);
+  const double rr = block_reduce_fixed(partial + RED_BLOCKS, RED_BLOCKS);
+  const double rz = sc[8 + parity];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[8 + (parity ^ 1)] = rz_new;
+    sc[2] = rz_new;
+    sc[3] = rr;
+  }
+  const T b = (T)(rz != 0.0 ? rz_new / rz : 0.0);
+  GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
+}
+
 __global__ void k_set_scalar(double *__restrict__ sc, int k, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) sc[k] = v;
 }
@@ -276,6 +340,29 @@ hipError_t launch_pcg_dir(int prec, int64_t n, const double *sc, const void *z, 
     k_pcg_dir<double><<<grid_for(n), BS, 0, s>>>(n, sc, (const double *)z, (double *)p);
   else
     k_pcg_dir<float><<<grid_for(n), BS, 0, s>>>(n, sc, (const float *)z, (float *)p);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
+                              const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
+                              double *partial, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_pcg_update2<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, nb_pq, pq_partial, (const double *)p,
+                                                    (const double *)q, (double *)x, (double *)r,
+                                                    (const double *)dinv, (double *)z, partial);
+  else
+    k_pcg_update2<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, nb_pq, pq_partial, (const float *)p,
+                                                   (const float *)q, (float *)x, (float *)r, (const float *)dinv,
+                                                   (float *)z, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_dir2(int prec, int64_t n, double *sc, int parity, const double *partial, const void *z,
+                           void *p, hipStream_t s) {
+  if (prec == HPMG_F64)
+    k_pcg_dir2<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const double *)z, (double *)p);
+  else
+    k_pcg_dir2<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const float *)z, (float *)p);
   return hipGetLastError();
 }
 
