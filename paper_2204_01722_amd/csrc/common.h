@@ -143,7 +143,6 @@ bool use_atomic_scatter();
 // Vector kernels.
 hipError_t launch_init_bc(int prec, int64_t n_nodes, const uint8_t *mask, const void *x, void *y,
                           hipStream_t s);  // y = mask ? x : 0
-hipError_t launch_fill_bc_one(int prec, int64_t n_nodes, const uint8_t *mask, void *y, hipStream_t s);
 hipError_t launch_cast_state(int64_t n, const double *a, float *b, hipStream_t s);
 hipError_t launch_dot(int prec, int64_t n, const void *x, const void *y, double *partial,
                       double *out, hipStream_t s);
@@ -160,16 +159,12 @@ hipError_t launch_jacobi_dot(int prec, int64_t n, const void *dinv, const void *
 hipError_t launch_dot_pair(int prec, int64_t n, const void *z, const void *a, const void *b,
                            double *partial, double *out, hipStream_t s);  // out = {z.a, z.b}
 hipError_t launch_cast(int64_t n, int to_prec, const void *x, void *y, hipStream_t s);
-hipError_t launch_mul(int prec, int64_t n, const void *a, const void *x, void *y, hipStream_t s);
 hipError_t launch_recip(int prec, int64_t n, void *x, hipStream_t s);
 hipError_t launch_cheb_first(int prec, int64_t n, const void *dinv, const void *b, const void *Ax,
                              void *r, void *d, void *x, double inv_theta, hipStream_t s);
 hipError_t launch_cheb_step(int prec, int64_t n, const void *dinv, void *r, const void *Ad, void *d,
                             void *x, double c1, double c2, hipStream_t s);
 
-hipError_t launch_pcg_update(int prec, int64_t n, double *sc, const void *p, const void *q, void *x, void *r,
-                             const void *dinv, void *z, double *partial, hipStream_t s);
-hipError_t launch_pcg_dir(int prec, int64_t n, const double *sc, const void *z, void *p, hipStream_t s);
 hipError_t launch_set_scalar(double *sc, int k, double v, hipStream_t s);
 
 size_t prec_size(int prec);

@@ -1587,11 +1587,6 @@ __global__ void k_build_emap(const int32_t *__restrict__ en, const uint8_t *__re
   emap[i] = w;
 }
 
-__global__ void k_zero_d(double *__restrict__ x, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = 0.0;
-}
-
 // Node-centric assembly: y[n] = sum of the node's element records, in the fixed order
 // of its incidence list; constrained components take `src` (or zero).
 template <typename T>

@@ -29,11 +29,6 @@ __global__ void k_init_bc(int64_t nn, const uint8_t *__restrict__ mask, const T 
   GRID_STRIDE(i, 3 * nn) { y[i] = (mask && x && mask[i]) ? x[i] : T(0); }
 }
 
-template <typename T>
-__global__ void k_fill_bc_one(int64_t nn, const uint8_t *__restrict__ mask, T *__restrict__ y) {
-  GRID_STRIDE(i, 3 * nn) { y[i] = (mask && mask[i]) ? T(1) : T(0); }
-}
-
 __global__ void k_cast_d2f(int64_t n, const double *__restrict__ a, float *__restrict__ b) {
   GRID_STRIDE(i, n) { b[i] = (float)a[i]; }
 }
@@ -60,11 +55,6 @@ __global__ void k_cg_update(int64_t n, T alpha, const T *__restrict__ p, const T
     x[i] += alpha * p[i];
     rout[i] = rin[i] - alpha * q[i];
   }
-}
-
-template <typename T>
-__global__ void k_mul(int64_t n, const T *__restrict__ a, const T *__restrict__ x, T *__restrict__ y) {
-  GRID_STRIDE(i, n) { y[i] = a[i] * x[i]; }
 }
 
 template <typename T>
@@ -198,61 +188,6 @@ __global__ __launch_bounds__(RED_BLOCKS) void k_final(const double *__restrict__
   }
 }
 
-// ---- device-resident Jacobi-PCG step (no host round trip per iteration) -------------
-// Scalar slots: sc[0] rz, sc[1] p.q, sc[2] rz_new, sc[3] r.r, sc[5] breakdown flag,
-// sc[6] beta.
-template <typename T>
-__global__ __launch_bounds__(BS) void k_pcg_update(int64_t n, const double *__restrict__ sc,
-                                                   const T *__restrict__ p, const T *__restrict__ q,
-                                                   T *__restrict__ x, T *__restrict__ r,
-                                                   const T *__restrict__ dinv, T *__restrict__ z,
-                                                   double *__restrict__ partial) {
-  const double pq = sc[1];
-  const T a = (T)(pq > 0.0 ? sc[0] / pq : 0.0);
-  double v[2] = {0.0, 0.0};
-  GRID_STRIDE(i, n) {
-    x[i] += a * p[i];
-    const T ri = r[i] - a * q[i];
-    r[i] = ri;
-    const T zi = dinv[i] * ri;
-    z[i] = zi;
-    v[0] += (double)ri * (double)zi;
-    v[1] += (double)ri * (double)ri;
-  }
-  block_store<2>(v, partial);
-}
-
-__global__ __launch_bounds__(RED_BLOCKS) void k_pcg_final(const double *__restrict__ partial, int nb,
-                                                          double *__restrict__ sc) {
-  __shared__ double s[RED_BLOCKS];
-  double tot[2];
-  for (int k = 0; k < 2; ++k) {
-    s[threadIdx.x] = threadIdx.x < (unsigned)nb ? partial[k * nb + threadIdx.x] : 0.0;
-    __syncthreads();
-    for (int w = RED_BLOCKS / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
-      __syncthreads();
-    }
-    tot[k] = s[0];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    const double rz_old = sc[0];
-    sc[6] = rz_old != 0.0 ? tot[0] / rz_old : 0.0;
-    sc[2] = tot[0];
-    sc[3] = tot[1];
-    sc[0] = tot[0];
-    if (!(sc[1] > 0.0)) sc[5] = 1.0;
-  }
-}
-
-template <typename T>
-__global__ __launch_bounds__(BS) void k_pcg_dir(int64_t n, const double *__restrict__ sc, const T *__restrict__ z,
-                                                T *__restrict__ p) {
-  const T b = (T)sc[6];
-  GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
-}
-
 // Sum of partial[0 .. nb) in a fixed order, identical in every workgroup (each thread
 // adds a strided subset in order, then a fixed tree).
 __device__ __forceinline__ double block_reduce_fixed(const double *__restrict__ partial, int nb) {
@@ -323,26 +258,6 @@ __global__ void k_set_scalar(double *__restrict__ sc, int k, double v) {
 
 }  // namespace
 
-hipError_t launch_pcg_update(int prec, int64_t n, double *sc, const void *p, const void *q, void *x, void *r,
-                             const void *dinv, void *z, double *partial, hipStream_t s) {
-  if (prec == HPMG_F64)
-    k_pcg_update<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, (const double *)p, (const double *)q, (double *)x,
-                                                   (double *)r, (const double *)dinv, (double *)z, partial);
-  else
-    k_pcg_update<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, (const float *)p, (const float *)q, (float *)x,
-                                                  (float *)r, (const float *)dinv, (float *)z, partial);
-  k_pcg_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_dir(int prec, int64_t n, const double *sc, const void *z, void *p, hipStream_t s) {
-  if (prec == HPMG_F64)
-    k_pcg_dir<double><<<grid_for(n), BS, 0, s>>>(n, sc, (const double *)z, (double *)p);
-  else
-    k_pcg_dir<float><<<grid_for(n), BS, 0, s>>>(n, sc, (const float *)z, (float *)p);
-  return hipGetLastError();
-}
-
 hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
                               const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
                               double *partial, hipStream_t s) {
@@ -402,11 +317,6 @@ hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, doubl
   return hipGetLastError();
 }
 
-hipError_t launch_fill_bc_one(int prec, int64_t nn, const uint8_t *mask, void *y, hipStream_t s) {
-  DISPATCH(prec, (k_fill_bc_one<double><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (double *)y)),
-           (k_fill_bc_one<float><<<grid_for(3 * nn), BS, 0, s>>>(nn, mask, (float *)y)));
-}
-
 hipError_t launch_cast_state(int64_t n, const double *a, float *b, hipStream_t s) {
   k_cast_d2f<<<grid_for(n), BS, 0, s>>>(n, a, b);
   return hipGetLastError();
@@ -440,11 +350,6 @@ hipError_t launch_cg_update(int prec, int64_t n, double alpha, const void *p, co
                                                            (double *)x, (const double *)rin, (double *)rout)),
            (k_cg_update<float><<<grid_for(n), BS, 0, s>>>(n, (float)alpha, (const float *)p, (const float *)q,
                                                           (float *)x, (const float *)rin, (float *)rout)));
-}
-
-hipError_t launch_mul(int prec, int64_t n, const void *a, const void *x, void *y, hipStream_t s) {
-  DISPATCH(prec, (k_mul<double><<<grid_for(n), BS, 0, s>>>(n, (const double *)a, (const double *)x, (double *)y)),
-           (k_mul<float><<<grid_for(n), BS, 0, s>>>(n, (const float *)a, (const float *)x, (float *)y)));
 }
 
 hipError_t launch_recip(int prec, int64_t n, void *x, hipStream_t s) {
