@@ -234,7 +234,7 @@ typedef struct {
   int cheb_degree;      /* operator applications per smoothing sweep (default 3) */
   double cheb_lo;       /* interval [lo, hi] * lambda_max (defaults 0.1, 1.1) */
   double cheb_hi;
-  int lanczos_its;      /* CG/Lanczos iterations for lambda_max (default 10) */
+  int lanczos_its;      /* CG/Lanczos iterations for lambda_max (default 10, at most 64) */
   double coarse_rtol;   /* coarsest-level Jacobi-PCG relative tolerance (1e-3) */
   int coarse_maxit;     /* its cap (default 10000) */
   int coarse_fixed_its; /* > 0: run exactly this many coarse iterations (tests) */
@@ -266,7 +266,9 @@ int hpmg_mg_set_state(hpmg_mg mg, const double *u, void *stream);
  * l = 0 .. n_levels-2).  Synchronises `stream` (reads CG coefficients). */
 int hpmg_mg_setup(hpmg_mg mg, const double *const *seeds, void *stream);
 /* z = M^{-1} r (one V-cycle, zero initial guess), double in and out.
- * Synchronises once per coarse iteration (convergence test) unless coarse_fixed_its. */
+ * The coarse solve's stopping test runs on the device; the host queues its iterations
+ * in batches (the first as long as the previous coarse solve) and synchronises once per
+ * batch to read the outcome, or never with coarse_fixed_its. */
 int hpmg_mg_vcycle(hpmg_mg mg, const double *r, double *z, void *stream);
 /* lambda_max estimate of a level and the last coarse-solve iteration count. */
 int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its);

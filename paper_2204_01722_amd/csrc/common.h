@@ -52,6 +52,14 @@ constexpr int64_t MAX_NODES = int64_t(1) << 28;
 
 constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
 
+// Device scalar slots of a multigrid handle used by the fused Jacobi-PCG: r.z (2), r.r
+// (3), breakdown flag (5), r.z of the current iteration, alternating (8, 9), stop flag
+// (10), completed iterations (11), r.r of the start (12); per-iteration alpha and beta
+// when recorded for the eigenvalue estimate (SC_ALPHA + k, SC_BETA + k, k < PCG_RECORD).
+constexpr int SC_STOP = 10, SC_COUNT = 11, SC_RR0 = 12;
+constexpr int PCG_RECORD = 64;
+constexpr int SC_ALPHA = 32, SC_BETA = SC_ALPHA + PCG_RECORD, SC_N = SC_BETA + PCG_RECORD;
+
 }  // namespace hpmg
 
 struct hpmg_op_s {
@@ -108,14 +116,20 @@ bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
 // Stored-mode apply whose assembly also writes per-workgroup partials of du . y
-// (ceil(N / 256) of them, in pq); the atomic scatter mode is not supported.
+// (ceil(N / 256) of them, in pq); the atomic scatter mode is not supported.  With
+// `stop` set, every kernel of the apply returns at once while *stop != 0.
 hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
-                               hipStream_t s);
+                               const double *stop, hipStream_t s);
+// Fused Jacobi-PCG iteration on the slots above; all kernels return at once while
+// sc[SC_STOP] != 0.  update2 records alpha in *alpha_rec, dir2 beta in *beta_rec (when
+// not null), counts the iteration in sc[SC_COUNT] and sets the stop flag on breakdown
+// or when r.r <= rtol2 * sc[SC_RR0] (rtol2 < 0: never).
+hipError_t launch_pcg_begin(double *sc, hipStream_t s);
 hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
                               const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
-                              double *partial, hipStream_t s);
+                              double *partial, double *alpha_rec, hipStream_t s);
 hipError_t launch_pcg_dir2(int prec, int64_t n, double *sc, int parity, const double *partial, const void *z,
-                           void *p, hipStream_t s);
+                           void *p, double rtol2, double *beta_rec, hipStream_t s);
 hipError_t launch_inject(int64_t nc, const int32_t *map, const double *uf, double *uc, hipStream_t s);
 hipError_t launch_state_initial(const hpmg_op_s &op, const double *u, hipStream_t s);
 hipError_t launch_body_load(const hpmg_op_s &op, const double *g, double *f_ext, hipStream_t s);
@@ -165,7 +179,6 @@ hipError_t launch_cheb_first(int prec, int64_t n, const void *dinv, const void *
 hipError_t launch_cheb_step(int prec, int64_t n, const void *dinv, void *r, const void *Ad, void *d,
                             void *x, double c1, double c2, hipStream_t s);
 
-hipError_t launch_set_scalar(double *sc, int k, double v, hipStream_t s);
 
 size_t prec_size(int prec);
 

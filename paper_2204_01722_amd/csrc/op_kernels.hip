@@ -673,8 +673,9 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const double *__restrict__ geo, const double *__restrict__ sinit,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
+    const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E, const double *__restrict__ stop) {
   constexpr int NH = MODE == 2 ? 16 : MODE == 3 ? 19 : 9;
+  if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
   // Per element: v [3][Q^3] (du, then its values at the points, then the nodal result)
   // and G [3][3][Q^3] (gradient, then the flux).
@@ -1268,7 +1269,9 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restri
 template <typename T>
 __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__restrict__ emap,
                                                           const T *__restrict__ K, const T *__restrict__ x,
-                                                          T *__restrict__ ev, int64_t E) {
+                                                          T *__restrict__ ev, int64_t E,
+                                                          const double *__restrict__ stop) {
+  if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
   __shared__ T sx[ELB * 24];
   __shared__ T sK[ELB * ELMAT_PACKED];
   const int t = threadIdx.x, el = t / 24, r = t % 24;
@@ -1626,7 +1629,9 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_assemble_dot(int64_t N, const int32_t *__restrict__ off,
                                                       const int32_t *__restrict__ inc, const T *__restrict__ ev,
                                                       const uint8_t *__restrict__ mask, const T *__restrict__ src,
-                                                      T *__restrict__ y, double *__restrict__ partial) {
+                                                      T *__restrict__ y, double *__restrict__ partial,
+                                                      const double *__restrict__ stop) {
+  if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
   __shared__ double red[256];
   const int64_t tile = xcd_tile();
   const int64_t n = tile * blockDim.x + threadIdx.x;
@@ -1766,7 +1771,7 @@ hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool
 
 template <typename T, int P, int Q>
 static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode, const double *u, const T *du,
-                              T *y, T *ev, hipStream_t s) {
+                              T *y, T *ev, const double *stop, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
   if constexpr (std::is_same<T, double>::value) {
@@ -1774,20 +1779,20 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
       if (!ev) return hipErrorInvalidValue;  // these kernels only write element records
       if (mode == HPMG_INITIAL_NATIVE)
         k_jacobian_lines<T, P, Q, 1><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       else if (mode == HPMG_INITIAL_TUNED)
         k_jacobian_lines<T, P, Q, 2><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       else
         k_jacobian_lines<T, P, Q, 3><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E);
+            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       return hipGetLastError();
     }
   }
   if (mode == HPMG_STORED && ev && use_line_kernels()) {
     k_jacobian_lines<T, P, Q, 0><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, nullptr, nullptr,
                                                                            tab, f.mu, f.lam, f.mu_e, f.lam_e, ev,
-                                                                           op.E);
+                                                                           op.E, stop);
     return hipGetLastError();
   }
   if (mode == HPMG_STORED) {
@@ -1801,17 +1806,19 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
 }
 
 template <typename T>
-static hipError_t assemble_or_dot(const hpmg_op_s &op, const T *du, T *y, double *pq, hipStream_t s) {
+static hipError_t assemble_or_dot(const hpmg_op_s &op, const T *du, T *y, double *pq, const double *stop,
+                                  hipStream_t s) {
   if (!pq) return assemble<T>(op, du, y, s);
   k_assemble_dot<T><<<grid1d(op.N, 256), 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask,
-                                                      du, y, pq);
+                                                      du, y, pq, stop);
   return hipGetLastError();
 }
 
 // pq != NULL: the assembly also writes per-workgroup partials of du . y (ceil(N / 256)).
+// stop != NULL: the stored-mode kernels return at once while *stop != 0.
 template <typename T>
 static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, const T *du, T *y, hipStream_t s,
-                             double *pq = nullptr) {
+                             double *pq = nullptr, const double *stop = nullptr) {
   const hpmg_op_s &f = op.fine ? *op.fine : op;
   const bool atom = use_atomic_scatter();
   if (atom) {
@@ -1822,25 +1829,26 @@ static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, con
   const int tprec = std::is_same<T, double>::value ? HPMG_F64 : HPMG_F32;
   if (mode == HPMG_STORED && !atom && op.P == 2 && op.elmat && op.elmat_prec == tprec &&
       op.elmat_version == f.state_version) {
-    k_elmat_apply<T><<<grid1d(op.E, ELB), ELB * 24, 0, s>>>(op.emap, (const T *)op.elmat, du, ev, op.E);
+    k_elmat_apply<T><<<grid1d(op.E, ELB), ELB * 24, 0, s>>>(op.emap, (const T *)op.elmat, du, ev, op.E, stop);
     hipError_t e2 = hipGetLastError();
     if (e2 != hipSuccess) return e2;
-    return assemble_or_dot<T>(op, du, y, pq, s);
+    return assemble_or_dot<T>(op, du, y, pq, stop, s);
   }
   hipError_t e = hipErrorInvalidValue;
 #define X(p, q) \
-  if (op.P == p && op.Q == q) e = jacobian_pq<T, p, q>(op, f, mode, u, du, y, ev, s);
+  if (op.P == p && op.Q == q) e = jacobian_pq<T, p, q>(op, f, mode, u, du, y, ev, stop, s);
   HPMG_PQ_LIST(X)
 #undef X
   if (e != hipSuccess || atom) return e;
-  return assemble_or_dot<T>(op, du, y, pq, s);
+  return assemble_or_dot<T>(op, du, y, pq, stop, s);
 }
 
 hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
-                               hipStream_t s) {
+                               const double *stop, hipStream_t s) {
   if (use_atomic_scatter()) return hipErrorInvalidValue;
-  if (prec == HPMG_F64) return jacobian_t<double>(op, HPMG_STORED, nullptr, (const double *)du, (double *)y, s, pq);
-  return jacobian_t<float>(op, HPMG_STORED, nullptr, (const float *)du, (float *)y, s, pq);
+  if (prec == HPMG_F64)
+    return jacobian_t<double>(op, HPMG_STORED, nullptr, (const double *)du, (double *)y, s, pq, stop);
+  return jacobian_t<float>(op, HPMG_STORED, nullptr, (const float *)du, (float *)y, s, pq, stop);
 }
 
 hipError_t launch_jacobian(const hpmg_op_s &op, int prec, int mode, const double *u, const void *du,

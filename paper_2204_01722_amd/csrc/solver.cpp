@@ -39,8 +39,8 @@ struct hpmg_mg_s {
   size_t bytes = 0;
   double *red = nullptr;     // reduction partials
   double *pq_part = nullptr; // per-workgroup partials of p.q from the coarse fused assembly
-  double *scal = nullptr;    // device scalars (8)
-  double *host = nullptr;    // pinned host mirror (8)
+  double *scal = nullptr;    // device scalars (SC_N)
+  double *host = nullptr;    // pinned host mirror (SC_N)
   // fine FP64 vectors for the Krylov and Newton drivers
   double *fr = nullptr, *fr2 = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr;
   double *nF = nullptr, *ndu = nullptr, *nut = nullptr, *nu0 = nullptr;
@@ -65,8 +65,10 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
     return p;
   };
   mg->red = reinterpret_cast<double *>(take(2 * RED_BLOCKS * sizeof(double) * 2));
-  mg->scal = reinterpret_cast<double *>(take(16 * sizeof(double)));
-  mg->pq_part = reinterpret_cast<double *>(take((size_t)((mg->lv.back().n / 3 + 255) / 256 + 1) * sizeof(double)));
+  mg->scal = reinterpret_cast<double *>(take(SC_N * sizeof(double)));
+  int64_t nmax = 0;
+  for (const Level &L : mg->lv) nmax = std::max<int64_t>(nmax, L.n / 3);
+  mg->pq_part = reinterpret_cast<double *>(take((size_t)((nmax + 255) / 256 + 1) * sizeof(double)));
   for (Level &L : mg->lv) {
     const size_t nb = (size_t)L.n * es;
     L.b = take(nb);
@@ -141,80 +143,57 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
   return hi;
 }
 
-// Jacobi-PCG on level L from x = 0 with right-hand side L.b.  fixed > 0 runs exactly
-// that many iterations; otherwise stops at ||r|| <= rtol ||b||.  Records the CG
-// coefficients when asked (eigenvalue estimate).
-// Same iteration with every scalar kept on the device; the host reads the residual
-// norm only every `check` iterations (at most check - 1 extra iterations).
-int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, int check, hipStream_t s,
-               int *its_out) {
+// Jacobi-PCG on level L from x = 0 with right-hand side L.b: fixed > 0 runs exactly that
+// many iterations (fewer on a breakdown, p.Ap <= 0), otherwise it stops at
+// ||r|| <= rtol ||b|| or after maxit iterations.  Every scalar stays on the device and
+// the stopping test runs there (after it fires, the kernels of later iterations return
+// at once), so the host queues iterations in batches and reads the scalars once per
+// batch: first `predict` iterations (the previous solve's count), then batches that
+// double from `check`.  With alphas and betas given, the CG coefficients are read back
+// (eigenvalue estimate; fixed <= PCG_RECORD).
+int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, int predict, int check,
+               hipStream_t s, int *its_out, std::vector<double> *alphas = nullptr,
+               std::vector<double> *betas = nullptr) {
   int st;
   double *sc = mg->scal;
+  const bool record = alphas && betas;
+  if (record && (fixed <= 0 || fixed > PCG_RECORD)) return fail(HPMG_ERR_ARG, "pcg: bad recording length");
   HPMG_HIP(launch_init_bc(prec, L.n / 3, nullptr, nullptr, L.x, s));
   HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, 0.0, L.b, L.r, s));
   HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, sc + 2, s));  // sc[2] = rz, sc[3] = rr
   HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.z, 0.0, L.z, L.d, s));
-  HPMG_HIP(hipMemcpyAsync(sc + 8, sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));  // sc[8] = rz
-  HPMG_HIP(launch_set_scalar(sc, 5, 0.0, s));
-  if ((st = read_scalars(mg, 4, s))) return st;
-  const double bn = std::sqrt(mg->host[3]);
-  *its_out = 0;
-  if (fixed <= 0 && bn == 0.0) return HPMG_OK;
+  HPMG_HIP(launch_pcg_begin(sc, s));
+  const size_t l = &L - mg->lv.data();
   const int limit = fixed > 0 ? fixed : maxit;
+  const double rtol2 = fixed > 0 ? -1.0 : rtol * rtol;
   const int nb_pq = (int)((L.n / 3 + 255) / 256);
-  int its = 0;
+  int queued = 0, its = limit;
+  int batch = fixed > 0 ? limit : std::max(check, predict), grow = check;
   // Four launches per iteration: element kernel, assembly fused with p.Ap, the update
   // (alpha from the p.Ap partials) and the direction (beta from the r.z partials).
-  while (its < limit) {
-    HPMG_HIP(launch_jacobian_dot(*L.op, prec, L.d, L.t, mg->pq_part, s));
-    const size_t l = &L - mg->lv.data();
-    if (l < 8) mg->n_applies[l]++;
-    const int parity = its & 1;
-    HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, L.x, L.r, L.dinv, L.z,
-                                mg->red, s));
-    HPMG_HIP(launch_pcg_dir2(prec, L.n, sc, parity, mg->red, L.z, L.d, s));
-    ++its;
-    if (fixed <= 0 && (its % check == 0 || its == limit)) {
-      if ((st = read_scalars(mg, 6, s))) return st;
-      if (mg->host[5] != 0.0 || std::sqrt(mg->host[3]) <= rtol * bn) break;
+  while (queued < limit) {
+    const int k = std::min(batch, limit - queued);
+    for (int i = 0; i < k; ++i, ++queued) {
+      const int parity = queued & 1;
+      HPMG_HIP(launch_jacobian_dot(*L.op, prec, L.d, L.t, mg->pq_part, sc + SC_STOP, s));
+      HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, L.x, L.r, L.dinv, L.z,
+                                  mg->red, record ? sc + SC_ALPHA + queued : nullptr, s));
+      HPMG_HIP(launch_pcg_dir2(prec, L.n, sc, parity, mg->red, L.z, L.d, rtol2,
+                               record ? sc + SC_BETA + queued : nullptr, s));
     }
+    if (fixed > 0 && !record) break;  // no read: the count is the fixed one
+    if ((st = read_scalars(mg, record ? SC_N : SC_RR0 + 1, s))) return st;
+    if (mg->host[SC_STOP] != 0.0 || queued >= limit) {
+      its = (int)mg->host[SC_COUNT];
+      break;
+    }
+    batch = grow;
+    grow = std::min(2 * grow, 64);
   }
-  *its_out = its;
-  return HPMG_OK;
-}
-
-int pcg(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, hipStream_t s, int *its_out,
-        std::vector<double> *alphas, std::vector<double> *betas) {
-  int st;
-  HPMG_HIP(launch_init_bc(prec, L.n / 3, nullptr, nullptr, L.x, s));
-  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.b, 0.0, L.b, L.r, s));
-  HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, mg->scal, s));
-  if ((st = read_scalars(mg, 2, s))) return st;
-  double rz = mg->host[0];
-  const double bn = std::sqrt(mg->host[1]);
-  *its_out = 0;
-  if (fixed <= 0 && bn == 0.0) return HPMG_OK;
-  HPMG_HIP(launch_waxpby(prec, L.n, 1.0, L.z, 0.0, L.z, L.d, s));
-  const int limit = fixed > 0 ? fixed : maxit;
-  int its = 0;
-  while (its < limit) {
-    if ((st = apply(mg, L, prec, L.d, L.t, s))) return st;
-    HPMG_HIP(launch_dot(prec, L.n, L.d, L.t, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 1, s))) return st;
-    const double pq = mg->host[0];
-    if (!(pq > 0.0)) break;
-    const double alpha = rz / pq;
-    HPMG_HIP(launch_cg_update(prec, L.n, alpha, L.d, L.t, L.x, L.r, L.r, s));
-    ++its;
-    if (alphas) alphas->push_back(alpha);
-    HPMG_HIP(launch_jacobi_dot(prec, L.n, L.dinv, L.r, L.z, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 2, s))) return st;
-    const double rz_new = mg->host[0];
-    if (fixed <= 0 && std::sqrt(mg->host[1]) <= rtol * bn) break;
-    const double beta = rz_new / rz;
-    if (betas) betas->push_back(beta);
-    HPMG_HIP(launch_axpby(prec, L.n, 1.0, L.z, beta, L.d, s));
-    rz = rz_new;
+  if (l < 8) mg->n_applies[l] += its;
+  if (record) {
+    alphas->assign(mg->host + SC_ALPHA, mg->host + SC_ALPHA + its);
+    betas->assign(mg->host + SC_BETA, mg->host + SC_BETA + its);
   }
   *its_out = its;
   return HPMG_OK;
@@ -249,7 +228,8 @@ int cycle(hpmg_mg_s *mg, int l, hipStream_t s) {
   Level &L = mg->lv[l];
   if (l + 1 == (int)mg->lv.size()) {
     int its = 0;
-    st = pcg_device(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its, 4, s, &its);
+    st = pcg_device(mg, L, prec, mg->prm.coarse_rtol, mg->prm.coarse_maxit, mg->prm.coarse_fixed_its,
+                    mg->last_coarse_its, 4, s, &its);
     mg->last_coarse_its = its;
     mg->n_coarse_its += its;
     return st;
@@ -345,7 +325,7 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
       HPMG_HIP(launch_cast(L.n, HPMG_F32, seeds[l], L.b, s));
     std::vector<double> al, be;
     int its = 0;
-    if ((st = pcg(mg, L, prec, 0.0, 0, mg->prm.lanczos_its, s, &its, &al, &be))) return st;
+    if ((st = pcg_device(mg, L, prec, 0.0, 0, mg->prm.lanczos_its, 0, 0, s, &its, &al, &be))) return st;
     if (al.empty()) return fail(HPMG_ERR_BREAKDOWN, "mg_setup: eigenvalue estimate broke down");
     std::vector<double> diag(al.size()), off(al.size() > 1 ? al.size() - 1 : 0);
     for (size_t j = 0; j < al.size(); ++j) {
@@ -439,7 +419,7 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
   if (params->precision != HPMG_F64 && params->precision != HPMG_F32)
     return fail(HPMG_ERR_ARG, "mg_create: bad precision");
   if (params->cheb_degree < 1 || !(params->cheb_lo > 0.0) || !(params->cheb_hi > params->cheb_lo) ||
-      params->lanczos_its < 1 || params->coarse_maxit < 1)
+      params->lanczos_its < 1 || params->lanczos_its > PCG_RECORD || params->coarse_maxit < 1)
     return fail(HPMG_ERR_ARG, "mg_create: bad smoother or coarse-solver parameters");
   const hpmg_op_s *f = levels[0];
   if (!f || f->fine) return fail(HPMG_ERR_ARG, "mg_create: levels[0] must be a fine operator");
@@ -477,7 +457,7 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
     L.redisc = l > 0 && redisc;
     mg->lv.push_back(L);
   }
-  if (hipHostMalloc((void **)&mg->host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void **)&mg->host, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete mg;
     return fail(HPMG_ERR_HIP, "mg_create: pinned host buffer");
   }

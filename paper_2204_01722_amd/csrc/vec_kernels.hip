@@ -205,9 +205,23 @@ __device__ __forceinline__ double block_reduce_fixed(const double *__restrict__ 
   return r;
 }
 
-// Fused Jacobi-PCG steps for the coarse solve.  The search direction's curvature p.q
-// arrives as workgroup partials of the fused assembly; rz alternates between scalar
-// slots 8 and 9 so that no workgroup overwrites a value another one still reads.
+// Fused Jacobi-PCG iteration (four launches: the operator's element kernel, its
+// assembly fused with the partials of p.q, update2 and dir2).  The curvature p.q arrives
+// as workgroup partials of the fused assembly; rz alternates between scalar slots 8 and
+// 9 so that no workgroup overwrites a value another one still reads.  The convergence
+// test runs on the device: dir2 raises sc[SC_STOP], after which every kernel of later
+// iterations returns at once, so the host can queue many iterations and read the
+// scalars rarely.
+__global__ void k_pcg_begin(double *__restrict__ sc) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    sc[8] = sc[2];
+    sc[SC_RR0] = sc[3];
+    sc[5] = 0.0;
+    sc[SC_STOP] = 0.0;
+    sc[SC_COUNT] = 0.0;
+  }
+}
+
 // update2: alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z, r.r.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restrict__ sc, int parity, int nb_pq,
@@ -215,13 +229,16 @@ __global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restric
                                                     const T *__restrict__ p, const T *__restrict__ q,
                                                     T *__restrict__ x, T *__restrict__ r,
                                                     const T *__restrict__ dinv, T *__restrict__ z,
-                                                    double *__restrict__ partial) {
+                                                    double *__restrict__ partial, double *__restrict__ alpha_rec) {
+  if (sc[SC_STOP] != 0.0) return;
   const double pq = block_reduce_fixed(pq_partial, nb_pq);
+  const double alpha = pq > 0.0 ? sc[8 + parity] / pq : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[1] = pq;
     if (!(pq > 0.0)) sc[5] = 1.0;
+    if (alpha_rec) *alpha_rec = alpha;
   }
-  const T a = (T)(pq > 0.0 ? sc[8 + parity] / pq : 0.0);
+  const T a = (T)alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
     x[i] += a * p[i];
@@ -235,60 +252,67 @@ __global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restric
   block_store<2>(v, partial);
 }
 
-// dir2: rz_new and r.r from the partials, beta = rz_new / rz, p = z + beta p.
+// dir2: rz_new and r.r from the partials, beta = rz_new / rz, p = z + beta p; counts the
+// iteration and decides whether to stop.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_pcg_dir2(int64_t n, double *__restrict__ sc, int parity,
                                                  const double *__restrict__ partial, const T *__restrict__ z,
-                                                 T *__restrict__ p) {
+                                                 T *__restrict__ p, double rtol2, double *__restrict__ beta_rec) {
+  if (sc[SC_STOP] != 0.0) return;
   const double rz_new = block_reduce_fixed(partial, RED_BLOCKS);
   const double rr = block_reduce_fixed(partial + RED_BLOCKS, RED_BLOCKS);
   const double rz = sc[8 + parity];
+  const bool broke = sc[5] != 0.0;
+  const double beta = rz != 0.0 ? rz_new / rz : 0.0;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc[8 + (parity ^ 1)] = rz_new;
-    sc[2] = rz_new;
-    sc[3] = rr;
+    if (broke) {
+      sc[SC_STOP] = 1.0;
+    } else {
+      sc[8 + (parity ^ 1)] = rz_new;
+      sc[2] = rz_new;
+      sc[3] = rr;
+      sc[SC_COUNT] += 1.0;
+      if (beta_rec) *beta_rec = beta;
+      if (rtol2 >= 0.0 && rr <= rtol2 * sc[SC_RR0]) sc[SC_STOP] = 1.0;
+    }
   }
-  const T b = (T)(rz != 0.0 ? rz_new / rz : 0.0);
+  if (broke) return;
+  const T b = (T)beta;
   GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
-}
-
-__global__ void k_set_scalar(double *__restrict__ sc, int k, double v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) sc[k] = v;
 }
 
 }  // namespace
 
+hipError_t launch_pcg_begin(double *sc, hipStream_t s) {
+  k_pcg_begin<<<1, 64, 0, s>>>(sc);
+  return hipGetLastError();
+}
+
 hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
                               const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
-                              double *partial, hipStream_t s) {
+                              double *partial, double *alpha_rec, hipStream_t s) {
   if (prec == HPMG_F64)
     k_pcg_update2<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, nb_pq, pq_partial, (const double *)p,
                                                     (const double *)q, (double *)x, (double *)r,
-                                                    (const double *)dinv, (double *)z, partial);
+                                                    (const double *)dinv, (double *)z, partial, alpha_rec);
   else
     k_pcg_update2<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, nb_pq, pq_partial, (const float *)p,
                                                    (const float *)q, (float *)x, (float *)r, (const float *)dinv,
-                                                   (float *)z, partial);
+                                                   (float *)z, partial, alpha_rec);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_dir2(int prec, int64_t n, double *sc, int parity, const double *partial, const void *z,
-                           void *p, hipStream_t s) {
+                           void *p, double rtol2, double *beta_rec, hipStream_t s) {
   if (prec == HPMG_F64)
-    k_pcg_dir2<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const double *)z, (double *)p);
+    k_pcg_dir2<double><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const double *)z, (double *)p, rtol2,
+                                                 beta_rec);
   else
-    k_pcg_dir2<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const float *)z, (float *)p);
+    k_pcg_dir2<float><<<RED_BLOCKS, BS, 0, s>>>(n, sc, parity, partial, (const float *)z, (float *)p, rtol2,
+                                                beta_rec);
   return hipGetLastError();
 }
 
-hipError_t launch_set_scalar(double *sc, int k, double v, hipStream_t s) {
-  k_set_scalar<<<1, 64, 0, s>>>(sc, k, v);
-  return hipGetLastError();
-}
-
-namespace {
-
-}  // namespace
 
 size_t prec_size(int prec) { return prec == HPMG_F64 ? sizeof(double) : sizeof(float); }
 
