@@ -239,7 +239,8 @@ typedef struct {
   int coarse_maxit;     /* its cap (default 10000) */
   int coarse_fixed_its; /* > 0: run exactly this many coarse iterations (tests) */
   int precision;        /* HPMG_F32: smoothing/transfer/coarse solve in FP32 */
-  int coarse_element_matrices; /* 1: order-1 coarsest level applied with element matrices */
+  int coarse_element_matrices; /* 1: order-1 Galerkin coarsest level from element matrices,
+                                  assembled into 3 x 3 node blocks for its Jacobi-PCG */
 } hpmg_mg_params;
 
 void hpmg_mg_default_params(hpmg_mg_params *p);

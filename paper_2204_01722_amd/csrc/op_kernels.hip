@@ -1295,6 +1295,61 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__rest
   ev[e * 24 + r] = acc;
 }
 
+// The order-1 operator assembled into 3 x 3 node blocks, sliced ELL by slot (column
+// node cols[j][n], -1 - n past the row's end: a zero block; entry (i, k) at
+// vals[j][n][3 i + k]: the three rows of a node are contiguous).  One
+// thread per (slot, row node) sums the block over the elements that hold both nodes,
+// in the row node's incidence order (so the result is reproducible), in double, and
+// masks it like the matrix-free apply: constrained columns are zero, constrained rows
+// identity rows.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ell_build(int64_t nn, int W, const int32_t *__restrict__ cols,
+                                                   const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
+                                                   const uint32_t *__restrict__ emap, const T *__restrict__ K,
+                                                   T *__restrict__ vals) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)W * nn) return;
+  const int j = (int)(t / nn);
+  const int64_t n = t - (int64_t)j * nn;
+  const int32_t c = cols[t];
+  if (c < 0) {  // padding: a zero block
+#pragma unroll
+    for (int m = 0; m < 9; ++m) vals[t * 9 + m] = T(0);
+    return;
+  }
+  double a[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) a[m] = 0.0;
+  uint32_t rbc = 0, cbc = 0;
+  for (int32_t k = off[n]; k < off[n + 1]; ++k) {
+    const int32_t rec = inc[k];
+    const int64_t e = rec / 8;
+    const int la = rec % 8;
+    rbc = (emap[rec] >> EMAP_BC_SHIFT) & 7u;
+    const T *Ke = K + e * ELMAT_PACKED;
+    for (int lb = 0; lb < 8; ++lb) {
+      const uint32_t wb = emap[e * 8 + lb];
+      if ((int32_t)(wb & EMAP_ID_MASK) != c) continue;
+      cbc = (wb >> EMAP_BC_SHIFT) & 7u;
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk) {
+          const int r = la * 3 + i, q = lb * 3 + kk;
+          a[i * 3 + kk] += (double)Ke[r <= q ? elmat_index(r, q) : elmat_index(q, r)];
+        }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int kk = 0; kk < 3; ++kk) {
+      double v = ((cbc >> kk) & 1u) ? 0.0 : a[i * 3 + kk];
+      if ((rbc >> i) & 1u) v = (c == n && i == kk) ? 1.0 : 0.0;
+      vals[t * 9 + i * 3 + kk] = (T)v;
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // a11: p-transfer on the same elements (eq. mg_prolong).
 // ------------------------------------------------------------------------------------
@@ -2035,6 +2090,19 @@ hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s) {
   X(2) X(3) X(4) X(5)
 #undef X
   return hipErrorInvalidValue;
+}
+
+hipError_t launch_ell_build(const hpmg_op_s &op, int prec, int64_t W, const int32_t *cols, void *vals,
+                            hipStream_t s) {
+  if (op.P != 2 || !op.elmat || op.elmat_prec != prec) return hipErrorInvalidValue;
+  const unsigned g = grid1d(W * op.N, 256);
+  if (prec == HPMG_F64)
+    k_ell_build<double><<<g, 256, 0, s>>>(op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
+                                          (const double *)op.elmat, (double *)vals);
+  else
+    k_ell_build<float><<<g, 256, 0, s>>>(op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
+                                         (const float *)op.elmat, (float *)vals);
+  return hipGetLastError();
 }
 
 hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s) {

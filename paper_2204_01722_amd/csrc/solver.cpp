@@ -28,6 +28,8 @@ struct Level {
   bool redisc = false;
   int32_t *inj = nullptr;
   double *ustate = nullptr;
+  // second direction buffer of the coarsest level (assembled-operator PCG)
+  void *p2 = nullptr;
 };
 
 }  // namespace
@@ -46,6 +48,15 @@ struct hpmg_mg_s {
   double *nF = nullptr, *ndu = nullptr, *nut = nullptr, *nu0 = nullptr;
   int last_coarse_its = 0;
   int setup_done = 0;
+  // Order-1 Galerkin coarsest level assembled into 3 x 3 node blocks, sliced ELL:
+  // column nodes [ell_w][N] (ascending per row, -1 - n past its end) and values
+  // [ell_w][9][N], rebuilt from the element matrices at every setup.
+  int ell_w = 0;
+  std::vector<int32_t> ell_cols_host;
+  int32_t *ell_cols = nullptr;
+  void *ell_vals = nullptr;
+  bool ell_ready = false;
+  uint64_t ell_version = 0;  // fine state version the blocks were built from
   // counters since creation: V-cycles, coarse iterations, operator applies per level
   int64_t n_vcycles = 0, n_coarse_its = 0, n_setups = 0;
   int64_t n_applies[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -68,7 +79,15 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   mg->scal = reinterpret_cast<double *>(take(SC_N * sizeof(double)));
   int64_t nmax = 0;
   for (const Level &L : mg->lv) nmax = std::max<int64_t>(nmax, L.n / 3);
-  mg->pq_part = reinterpret_cast<double *>(take((size_t)((nmax + 255) / 256 + 1) * sizeof(double)));
+  const int64_t nb_pq = std::max<int64_t>((nmax + 255) / 256, ell_pcg_blocks(mg->lv.back().n / 3, mg->ell_w));
+  mg->pq_part = reinterpret_cast<double *>(take((size_t)(nb_pq + 1) * sizeof(double)));
+  if (mg->ell_w > 0) {
+    Level &C = mg->lv.back();
+    const size_t nn = (size_t)(C.n / 3);
+    mg->ell_cols = reinterpret_cast<int32_t *>(take((size_t)mg->ell_w * nn * sizeof(int32_t)));
+    mg->ell_vals = take((size_t)mg->ell_w * 9 * nn * es);
+    C.p2 = take((size_t)C.n * es);
+  }
   for (Level &L : mg->lv) {
     const size_t nb = (size_t)L.n * es;
     L.b = take(nb);
@@ -166,15 +185,29 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
   const size_t l = &L - mg->lv.data();
   const int limit = fixed > 0 ? fixed : maxit;
   const double rtol2 = fixed > 0 ? -1.0 : rtol * rtol;
-  const int nb_pq = (int)((L.n / 3 + 255) / 256);
+  // The assembled coarsest level (when its blocks match the current linearisation)
+  // takes two launches per iteration; otherwise four.
+  const bool ell = !record && l + 1 == mg->lv.size() && mg->ell_ready &&
+                   mg->ell_version == mg->lv[0].op->state_version;
+  const int64_t nn = L.n / 3;
+  const int nb_pq = ell ? ell_pcg_blocks(nn, mg->ell_w) : (int)((nn + 255) / 256);
   int queued = 0, its = limit;
   int batch = fixed > 0 ? limit : std::max(check, predict), grow = check;
-  // Four launches per iteration: element kernel, assembly fused with p.Ap, the update
-  // (alpha from the p.Ap partials) and the direction (beta from the r.z partials).
   while (queued < limit) {
     const int k = std::min(batch, limit - queued);
     for (int i = 0; i < k; ++i, ++queued) {
       const int parity = queued & 1;
+      if (ell) {
+        // Direction of iteration `queued` in (L.d, L.p2)[parity], the previous one in the other.
+        void *pn = parity ? L.p2 : L.d, *po = parity ? L.d : L.p2;
+        HPMG_HIP(launch_ell_pcg_apply(prec, nn, mg->ell_w, mg->ell_cols, mg->ell_vals, L.z, po, pn, L.t, sc,
+                                      mg->red, queued, rtol2, mg->pq_part, s));
+        HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, pn, L.t, L.x, L.r, L.dinv, L.z,
+                                    mg->red, nullptr, s));
+        continue;
+      }
+      // Element kernel, assembly fused with p.Ap, the update (alpha from the p.Ap
+      // partials) and the direction (beta from the r.z partials).
       HPMG_HIP(launch_jacobian_dot(*L.op, prec, L.d, L.t, mg->pq_part, sc + SC_STOP, s));
       HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, L.x, L.r, L.dinv, L.z,
                                   mg->red, record ? sc + SC_ALPHA + queued : nullptr, s));
@@ -182,6 +215,9 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
                                record ? sc + SC_BETA + queued : nullptr, s));
     }
     if (fixed > 0 && !record) break;  // no read: the count is the fixed one
+    // the stopping test of the last queued iteration
+    if (ell) HPMG_HIP(launch_ell_pcg_apply(prec, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, sc,
+                                           mg->red, queued, rtol2, nullptr, s));
     if ((st = read_scalars(mg, record ? SC_N : SC_RR0 + 1, s))) return st;
     if (mg->host[SC_STOP] != 0.0 || queued >= limit) {
       its = (int)mg->host[SC_COUNT];
@@ -261,6 +297,44 @@ int vcycle(hpmg_mg_s *mg, const double *r, double *z, hipStream_t s) {
   return HPMG_OK;
 }
 
+// Sparsity of the assembled order-1 coarsest level: the nodes that share an element
+// with each node, ascending.  Rows longer than ELL_MAX_W (not possible on hexahedral
+// meshes whose nodes touch at most 8 elements) leave the level matrix-free.
+constexpr int ELL_MAX_W = 64;
+int build_ell_structure(hpmg_mg_s *mg) {
+  const hpmg_op_s &C = *mg->lv.back().op;
+  const int64_t nn = C.N, nrec = C.E * 8;
+  std::vector<int32_t> en(nrec);
+  HPMG_HIP(hipMemcpy(en.data(), C.elem_nodes, nrec * sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int32_t> nb((size_t)nn * ELL_MAX_W), cnt(nn, 0);
+  for (int64_t e = 0; e < C.E; ++e)
+    for (int a = 0; a < 8; ++a) {
+      const int32_t n = en[e * 8 + a];
+      if (n < 0 || n >= nn) return fail(HPMG_ERR_SHAPE, "mg_create: bad node id in the coarsest level");
+      int32_t *row = nb.data() + (size_t)n * ELL_MAX_W;
+      for (int b = 0; b < 8; ++b) {
+        const int32_t c = en[e * 8 + b];
+        bool seen = false;
+        for (int k = 0; k < cnt[n] && !seen; ++k) seen = row[k] == c;
+        if (seen) continue;
+        if (cnt[n] == ELL_MAX_W) return HPMG_OK;  // too wide: stay matrix-free
+        row[cnt[n]++] = c;
+      }
+    }
+  int w = 0;
+  for (int64_t n = 0; n < nn; ++n) {
+    std::sort(nb.begin() + n * ELL_MAX_W, nb.begin() + n * ELL_MAX_W + cnt[n]);
+    w = std::max(w, cnt[n]);
+  }
+  // padding slots hold -1 - n: the node itself, with a zero block
+  mg->ell_cols_host.resize((size_t)w * nn);
+  for (int64_t n = 0; n < nn; ++n)
+    for (int k = 0; k < w; ++k)
+      mg->ell_cols_host[(size_t)k * nn + n] = k < cnt[n] ? nb[(size_t)n * ELL_MAX_W + k] : (int32_t)(-1 - n);
+  mg->ell_w = w;
+  return HPMG_OK;
+}
+
 int mg_check(hpmg_mg_s *mg, const char *fn) {
   if (!mg) return fail(HPMG_ERR_ARG, std::string(fn) + ": null multigrid handle");
   if (!mg->ws) return fail(HPMG_ERR_WORKSPACE, std::string(fn) + ": workspace not bound");
@@ -312,10 +386,16 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
     HPMG_HIP(launch_recip(prec, L.n, L.dinv, s));
   }
   Level &Lc = mg->lv.back();
+  mg->ell_ready = false;
   if (mg->prm.coarse_element_matrices && Lc.op->P == 2 && Lc.op->elmat) {
     HPMG_HIP(launch_elmat_build(*Lc.op, prec, s));
     Lc.op->elmat_prec = prec;
     Lc.op->elmat_version = fine->state_version;
+    if (mg->ell_w > 0) {
+      HPMG_HIP(launch_ell_build(*Lc.op, prec, mg->ell_w, mg->ell_cols, mg->ell_vals, s));
+      mg->ell_ready = true;
+      mg->ell_version = fine->state_version;
+    }
   }
   for (size_t l = 0; l + 1 < mg->lv.size(); ++l) {
     Level &L = mg->lv[l];
@@ -457,6 +537,13 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
     L.redisc = l > 0 && redisc;
     mg->lv.push_back(L);
   }
+  if (!redisc && params->coarse_element_matrices && mg->lv.back().op->P == 2) {
+    const int st = build_ell_structure(mg);
+    if (st) {
+      delete mg;
+      return st;
+    }
+  }
   if (hipHostMalloc((void **)&mg->host, SC_N * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     delete mg;
     return fail(HPMG_ERR_HIP, "mg_create: pinned host buffer");
@@ -485,6 +572,10 @@ int hpmg_mg_bind_workspace(hpmg_mg mg, void *ws, size_t bytes) {
   mg->bytes = bytes;
   mg_layout(mg, mg->ws);
   mg->setup_done = 0;
+  mg->ell_ready = false;
+  if (mg->ell_w > 0)
+    HPMG_HIP(hipMemcpy(mg->ell_cols, mg->ell_cols_host.data(), mg->ell_cols_host.size() * sizeof(int32_t),
+                       hipMemcpyHostToDevice));
   // Injection maps of rediscretised levels: coarse local node (a1, a2, a3) of an
   // element sits at fine local node (s a1, s a2, s a3), s = (Pf - 1) / (Pc - 1).
   for (size_t l = 1; l < mg->lv.size(); ++l) {

@@ -188,21 +188,40 @@ __global__ __launch_bounds__(RED_BLOCKS) void k_final(const double *__restrict__
   }
 }
 
-// Sum of partial[0 .. nb) in a fixed order, identical in every workgroup (each thread
-// adds a strided subset in order, then a fixed tree).
-__device__ __forceinline__ double block_reduce_fixed(const double *__restrict__ partial, int nb) {
-  __shared__ double s[BS];
-  double t = 0.0;
-  for (int i = threadIdx.x; i < nb; i += BS) t += partial[i];
-  s[threadIdx.x] = t;
-  __syncthreads();
-  for (int w = BS / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < (unsigned)w) s[threadIdx.x] += s[threadIdx.x + w];
-    __syncthreads();
+// NV sums of partial[v * stride + 0 .. nb) by the whole workgroup in a fixed order
+// (strided per-thread sums, a wave butterfly, the waves in order); every thread gets
+// the results.
+template <int NV>
+__device__ __forceinline__ void block_reduce_fixed_n(const double *__restrict__ partial, int nb, int stride,
+                                                     double (&out)[NV]) {
+  __shared__ double s[NV][BS / 64];
+  double t[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) t[v] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += BS)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) t[v] += partial[v * stride + i];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    t[v] = wave_sum(t[v]);
+    if (lane == 0) s[v][wid] = t[v];
   }
-  const double r = s[0];
   __syncthreads();
-  return r;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS / 64; ++w) r += s[v][w];
+    out[v] = r;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double block_reduce_fixed(const double *__restrict__ partial, int nb) {
+  double o[1];
+  block_reduce_fixed_n<1>(partial, nb, 0, o);
+  return o[0];
 }
 
 // Fused Jacobi-PCG iteration (four launches: the operator's element kernel, its
@@ -259,8 +278,9 @@ __global__ __launch_bounds__(BS) void k_pcg_dir2(int64_t n, double *__restrict__
                                                  const double *__restrict__ partial, const T *__restrict__ z,
                                                  T *__restrict__ p, double rtol2, double *__restrict__ beta_rec) {
   if (sc[SC_STOP] != 0.0) return;
-  const double rz_new = block_reduce_fixed(partial, RED_BLOCKS);
-  const double rr = block_reduce_fixed(partial + RED_BLOCKS, RED_BLOCKS);
+  double red2[2];
+  block_reduce_fixed_n<2>(partial, RED_BLOCKS, RED_BLOCKS, red2);
+  const double rz_new = red2[0], rr = red2[1];
   const double rz = sc[8 + parity];
   const bool broke = sc[5] != 0.0;
   const double beta = rz != 0.0 ? rz_new / rz : 0.0;
@@ -281,10 +301,125 @@ __global__ __launch_bounds__(BS) void k_pcg_dir2(int64_t n, double *__restrict__
   GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
 }
 
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Jacobi-PCG iteration `it` on an assembled operator held as 3 x 3 blocks in sliced ELL
+// (slot j of node n: column node cols[j][n], or -1 - n for padding past the row's end,
+// whose block is zero; entry (i, k) of the block at vals[j][n][3 i + k]), replacing the
+// element kernel, the fused assembly and dir2 of the four-launch iteration.  Prologue
+// (it > 0, every workgroup alike): r.z and r.r of iteration it - 1 from the update's
+// partials, beta, the stopping test (as in dir2; the count is set, not incremented, so
+// a repeated prologue changes nothing).  Body, by scalar rows, the three rows of a node
+// on neighbouring lanes (they read the same column nodes): the new direction
+// p = z + beta p_old is formed on the fly for every column node read, with one fused
+// multiply-add, so all threads that need a node's p agree bit for bit; the row's own
+// value goes to p_new (p_old and p_new alternate between two buffers), q = A p to y,
+// and the partial of p.q to pq_part[workgroup].  WC > 0 fixes the width at compile
+// time, so the row's loads can be issued in large groups.
+// nn = 0 runs the prologue alone.
+template <typename T, int WC>
+__global__ __launch_bounds__(BS) void k_ell_pcg_apply(int64_t nn, int W, const int32_t *__restrict__ cols,
+                                                      const T *__restrict__ vals, const T *__restrict__ z,
+                                                      const T *__restrict__ p_old, T *__restrict__ p_new,
+                                                      T *__restrict__ y, double *__restrict__ sc,
+                                                      const double *__restrict__ partial, int it, double rtol2,
+                                                      double *__restrict__ pq_part) {
+  if (sc[SC_STOP] != 0.0) return;
+  double beta = 0.0;
+  if (it > 0) {
+    double red2[2];
+    block_reduce_fixed_n<2>(partial, RED_BLOCKS, RED_BLOCKS, red2);
+    const double rz_new = red2[0], rr = red2[1];
+    const double rz = sc[8 + ((it - 1) & 1)];
+    const bool broke = sc[5] != 0.0;
+    const bool conv = !broke && rtol2 >= 0.0 && rr <= rtol2 * sc[SC_RR0];
+    beta = rz != 0.0 ? rz_new / rz : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (!broke) {
+        sc[8 + (it & 1)] = rz_new;
+        sc[2] = rz_new;
+        sc[3] = rr;
+        sc[SC_COUNT] = (double)it;
+      }
+      if (broke || conv) sc[SC_STOP] = 1.0;
+    }
+    if (broke || conv) return;
+  }
+  if (nn == 0) return;
+  const bool first = it == 0;
+  const T b = (T)beta;
+  double v[1] = {0.0};
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (t < 3 * nn) {
+    const int64_t n = t / 3;
+    const int i = (int)(t - 3 * n);
+    // direction value of node c, component k (the same expression wherever it is formed)
+    auto pdir = [&](int64_t c, int k) { return first ? z[c * 3 + k] : fma_t(b, p_old[c * 3 + k], z[c * 3 + k]); };
+    auto slot = [&](int j, int32_t c0) {
+      const int64_t c = c0 < 0 ? -1 - (int64_t)c0 : (int64_t)c0;
+      const T *A = vals + ((int64_t)j * nn + n) * 9 + 3 * i;
+      return A[0] * pdir(c, 0) + A[1] * pdir(c, 1) + A[2] * pdir(c, 2);
+    };
+    T acc = 0;
+    if constexpr (WC > 0) {
+      // all column ids first (one wait), then the blocks in groups whose loads are
+      // issued together (9 in FP32, 3 in FP64, as the registers allow)
+      constexpr int UR = sizeof(T) == 4 ? 9 : 3;
+      static_assert(WC % UR == 0, "width must be a multiple of the unroll");
+      int32_t cj[WC];
+#pragma unroll
+      for (int j = 0; j < WC; ++j) cj[j] = cols[(int64_t)j * nn + n];
+      for (int j0 = 0; j0 < WC; j0 += UR) {
+        T part[UR];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) part[u] = slot(j0 + u, cj[j0 + u]);
+#pragma unroll
+        for (int u = 0; u < UR; ++u) acc += part[u];
+      }
+    } else {
+      for (int j = 0; j < W; ++j) acc += slot(j, cols[(int64_t)j * nn + n]);
+    }
+    const T pn = pdir(n, i);
+    p_new[t] = pn;
+    y[t] = acc;
+    v[0] = (double)pn * (double)acc;
+  }
+  block_store<1>(v, pq_part);
+}
+
 }  // namespace
 
 hipError_t launch_pcg_begin(double *sc, hipStream_t s) {
   k_pcg_begin<<<1, 64, 0, s>>>(sc);
+  return hipGetLastError();
+}
+
+int ell_pcg_blocks(int64_t nn, int W) {
+  (void)W;
+  return (int)((3 * nn + BS - 1) / BS);
+}
+
+hipError_t launch_ell_pcg_apply(int prec, int64_t nn, int W, const int32_t *cols, const void *vals, const void *z,
+                                const void *p_old, void *p_new, void *y, double *sc, const double *partial, int it,
+                                double rtol2, double *pq_part, hipStream_t s) {
+  const unsigned g = nn > 0 ? (unsigned)ell_pcg_blocks(nn, W) : 1u;
+#define ELL_LAUNCH(TT, WC)                                                                                    \
+  k_ell_pcg_apply<TT, WC><<<g, BS, 0, s>>>(nn, W, cols, (const TT *)vals, (const TT *)z, (const TT *)p_old,    \
+                                           (TT *)p_new, (TT *)y, sc, partial, it, rtol2, pq_part)
+  // 27: every node of a hexahedral mesh interior
+  if (prec == HPMG_F64) {
+    if (W == 27)
+      ELL_LAUNCH(double, 27);
+    else
+      ELL_LAUNCH(double, 0);
+  } else {
+    if (W == 27)
+      ELL_LAUNCH(float, 27);
+    else
+      ELL_LAUNCH(float, 0);
+  }
+#undef ELL_LAUNCH
   return hipGetLastError();
 }
 
