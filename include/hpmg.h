@@ -153,7 +153,8 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
  * of this level's Galerkin operator from the fine operator's stored linearisation
  * (the element-level triple product B^T D B of Section III-D), in `precision`.  While
  * the fine linearisation is unchanged, stored-mode applies of this operator in that
- * precision then read the element matrices (symmetric: 300 scalars per element)
+ * precision then read the element matrices (symmetric: 300 scalars per element;
+ * HPMG_F32 builds them in FP32 from the FP32 state, after hpmg_state_cast_f32)
  * instead of the fine-quadrature linearisation.  A new stored linearisation makes them
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);

@@ -450,6 +450,8 @@ int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream) {
   if (!op->fine || op->P != 2 || !op->elmat)
     return fail(HPMG_ERR_UNSUPPORTED, "assemble_elements: only for coarse operators of order 1");
   if (!op->fine->state_ready) return fail(HPMG_ERR_ARG, "assemble_elements: no stored linearisation");
+  if (precision == HPMG_F32 && !op->fine->state32_ready)
+    return fail(HPMG_ERR_ARG, "assemble_elements: FP32 state not cast");
   HPMG_HIP(launch_elmat_build(*op, precision, S(stream)));
   op->elmat_prec = precision;
   op->elmat_version = op->fine->state_version;

@@ -1188,14 +1188,16 @@ constexpr int ELB = 8;  // elements per workgroup (8 x 24 = 192 threads)
 constexpr int ELMAT_PACKED = 300;  // 24 x 25 / 2 entries of the symmetric element matrix
 __device__ __forceinline__ constexpr int elmat_index(int r, int j) { return r * (47 - r) / 2 + j; }
 
-template <typename TO, int Q>
-__global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restrict__ state,
-                                                          const double *__restrict__ tab, double mu0,
+// T: precision of the state, tables, arithmetic and result (FP32 for the mixed-precision
+// preconditioner, FP64 otherwise).
+template <typename T, int Q>
+__global__ __launch_bounds__(ELB * 24) void k_elmat_build(const T *__restrict__ state,
+                                                          const T *__restrict__ tab, double mu0,
                                                           double lam0, const double *__restrict__ mu_e,
                                                           const double *__restrict__ lam_e,
-                                                          TO *__restrict__ K, int64_t E) {
+                                                          T *__restrict__ K, int64_t E) {
   constexpr int Q3 = Q * Q * Q, ET = QT<Q>::ET, NQ = QT<Q>::NQ;
-  __shared__ double sB[Q * 2], sG[Q * 2];
+  __shared__ T sB[Q * 2], sG[Q * 2];
   const int t = threadIdx.x, el = t / 24, j = t % 24;
   const int64_t e = (int64_t)blockIdx.x * ELB + el;
   if (t < 2 * Q) {
@@ -1205,42 +1207,42 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restri
   __syncthreads();
   if (e >= E) return;
   const int b = j / 3, k = j % 3, b1 = b & 1, b2 = (b >> 1) & 1, b3 = b >> 2;
-  const double mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
-  const double *s = state + ((e / ET) * NSTATE) * NQ + (e % ET) * Q3;
-  double acc[24];
+  const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
+  const T *s = state + ((e / ET) * NSTATE) * NQ + (e % ET) * Q3;
+  T acc[24];
 #pragma unroll
-  for (int r = 0; r < 24; ++r) acc[r] = 0.0;
+  for (int r = 0; r < 24; ++r) acc[r] = T(0);
   for (int q = 0; q < Q3; ++q) {
     const int q1 = q % Q, q2 = (q / Q) % Q, q3 = q / (Q * Q);
-    double A[3][3], tau[6];
+    T A[3][3], tau[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) A[a][jj] = s[(a * 3 + jj) * NQ + q];
 #pragma unroll
     for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ + q];
-    const double c = s[15 * NQ + q], W = s[16 * NQ + q];
+    const T c = s[15 * NQ + q], W = s[16 * NQ + q];
     // reference gradient of basis b at q
-    const double Bx = sB[q1 * 2 + b1], By = sB[q2 * 2 + b2], Bz = sB[q3 * 2 + b3];
-    const double Gx = sG[q1 * 2 + b1], Gy = sG[q2 * 2 + b2], Gz = sG[q3 * 2 + b3];
-    const double dp[3] = {Gx * By * Bz, Bx * Gy * Bz, Bx * By * Gz};
-    double v[3], w[3];
+    const T Bx = sB[q1 * 2 + b1], By = sB[q2 * 2 + b2], Bz = sB[q3 * 2 + b3];
+    const T Gx = sG[q1 * 2 + b1], Gy = sG[q2 * 2 + b2], Gz = sG[q3 * 2 + b3];
+    const T dp[3] = {Gx * By * Bz, Bx * Gy * Bz, Bx * By * Gz};
+    T v[3], w[3];
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj) v[jj] = dp[0] * A[0][jj] + dp[1] * A[1][jj] + dp[2] * A[2][jj];
 #pragma unroll
     for (int jj = 0; jj < 3; ++jj)
       w[jj] = v[0] * tau[sym_index(0, jj)] + v[1] * tau[sym_index(1, jj)] + v[2] * tau[sym_index(2, jj)];
     // s = g tau + lambda tr(g) I + (mu - c)(g + g^T), g = e_k v^T
-    double sm[3][3];
+    T sm[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int jj = 0; jj < 3; ++jj) {
-        double val = (i == k ? w[jj] + (mu - c) * v[jj] : 0.0) + (jj == k ? (mu - c) * v[i] : 0.0);
+        T val = (i == k ? w[jj] + (mu - c) * v[jj] : T(0)) + (jj == k ? (mu - c) * v[i] : T(0));
         if (i == jj) val += lam * v[k];
         sm[i][jj] = val;
       }
-    double f[3][3];
+    T f[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
@@ -1248,19 +1250,19 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const double *__restri
 #pragma unroll
     for (int a = 0; a < 8; ++a) {
       const int a1 = a & 1, a2 = (a >> 1) & 1, a3 = a >> 2;
-      const double ax = sB[q1 * 2 + a1], ay = sB[q2 * 2 + a2], az = sB[q3 * 2 + a3];
-      const double gx = sG[q1 * 2 + a1], gy = sG[q2 * 2 + a2], gz = sG[q3 * 2 + a3];
-      const double d0 = gx * ay * az, d1 = ax * gy * az, d2 = ax * ay * gz;
+      const T ax = sB[q1 * 2 + a1], ay = sB[q2 * 2 + a2], az = sB[q3 * 2 + a3];
+      const T gx = sG[q1 * 2 + a1], gy = sG[q2 * 2 + a2], gz = sG[q3 * 2 + a3];
+      const T d0 = gx * ay * az, d1 = ax * gy * az, d2 = ax * ay * gz;
 #pragma unroll
       for (int i = 0; i < 3; ++i) acc[a * 3 + i] += d0 * f[i][0] + d1 * f[i][1] + d2 * f[i][2];
     }
   }
   // The matrix is symmetric: store its upper triangle, row-major (entry (r, j), r <= j,
   // at r (47 - r) / 2 + j); column j supplies rows r <= j.
-  TO *out = K + (int64_t)e * ELMAT_PACKED;
+  T *out = K + (int64_t)e * ELMAT_PACKED;
 #pragma unroll
   for (int r = 0; r < 24; ++r)
-    if (r <= j) out[elmat_index(r, j)] = (TO)acc[r];
+    if (r <= j) out[elmat_index(r, j)] = acc[r];
 }
 
 // y_e = K_e x_e for order-1 elements (records for the node-centric assembly).  The
@@ -2083,7 +2085,7 @@ hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s) {
       k_elmat_build<double, q><<<g, ELB * 24, 0, s>>>(f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e, \
                                                       op.elmat, op.E);                               \
     else                                                                                              \
-      k_elmat_build<float, q><<<g, ELB * 24, 0, s>>>(f.state64, op.tab64, f.mu, f.lam, f.mu_e, f.lam_e,  \
+      k_elmat_build<float, q><<<g, ELB * 24, 0, s>>>(f.state32, op.tab32, f.mu, f.lam, f.mu_e, f.lam_e,  \
                                                      (float *)op.elmat, op.E);                        \
     return hipGetLastError();                                                                         \
   }

@@ -66,6 +66,31 @@ def test_vcycle_matches_oracle(n, orders, faces):
         assert rel(z, ref) < tol, (prec, rel(z, ref))
 
 
+@pytest.mark.parametrize("n,orders", [(3, [2, 1]), (2, [4, 2, 1])])
+def test_vcycle_coarse_tolerance_matches_oracle(n, orders):
+    """Coarse Jacobi-PCG to a relative tolerance (stopping test on the device, iterations
+    queued in batches): the V-cycle and the coarse iteration count equal the oracle's,
+    whose PCG tests the residual after every iteration; the same with the order-1 level
+    applied from element matrices (assembled node blocks) and matrix-free."""
+    from paper_2204_01722_amd.binding import PMG
+    print_case("vcycle_coarse_rtol", n=n, orders=orders)
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m, H, u = _build(n, orders, faces)
+    V = _oracle_vcycle(m, H, u, coarse_fixed=None)
+    fr = 1.0 - H.masks[0].reshape(-1)
+    rs = [inputs.random_vector(m.n_nodes, 23 + k).reshape(-1) * fr for k in range(3)]
+    refs = [V(r) for r in rs]
+    assert min(V.coarse_its) > 4
+    for elmat in (True, False):
+        pmg = PMG(H.ops, precision="f64", coarse_rtol=1e-3, coarse_element_matrices=elmat)
+        pmg.setup(H.seeds(7))
+        for r, ref, its_ref in zip(rs, refs, V.coarse_its):
+            z = t2n(pmg.vcycle(_dev(r.reshape(-1, 3))))
+            _, its = pmg.info(len(orders) - 1)
+            assert its == its_ref, (elmat, its, its_ref)
+            assert rel(z, ref) < 1e-10, (elmat, rel(z, ref))
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_fcg_matches_direct_solve(prec):
     from paper_2204_01722_amd.binding import PMG
