@@ -149,13 +149,14 @@ int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void 
  *   rebuilt per point) from the same buffer (fine operators, HPMG_F64 only). */
 int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, const void *du,
                         void *y, void *stream);
-/* Order-1 coarse operators only (Pc = 2): builds the dense 24 x 24 element matrices
- * of this level's Galerkin operator from the fine operator's stored linearisation
- * (the element-level triple product B^T D B of Section III-D), in `precision`.  While
- * the fine linearisation is unchanged, stored-mode applies of this operator in that
+/* Order-1 operators only (P = 2): builds the dense 24 x 24 element matrices of the
+ * operator from its stored linearisation (the element-level triple product B^T D B of
+ * Section III-D), in `precision`: for a Galerkin coarse operator the fine operator's
+ * linearisation on the fine quadrature, for a stand-alone one its own.  While that
+ * linearisation is unchanged, stored-mode applies of this operator in that
  * precision then read the element matrices (symmetric: 300 scalars per element;
  * HPMG_F32 builds them in FP32 from the FP32 state, after hpmg_state_cast_f32)
- * instead of the fine-quadrature linearisation.  A new stored linearisation makes them
+ * instead of the quadrature-point linearisation.  A new stored linearisation makes them
  * stale; applies fall back to the quadrature form until they are rebuilt. */
 int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream);
 

@@ -76,7 +76,7 @@ Layout layout_of(const hpmg_op_s *op) {
   L.csr_off = o; o += align256(((size_t)op->N + 1) * sizeof(int32_t));
   L.csr_inc = o; o += align256(nrec * sizeof(int32_t));
   L.evec = o; o += align256(nrec * 3 * sizeof(double));
-  L.elmat = o; o += (op->fine && op->P == 2) ? align256((size_t)op->E * 300 * sizeof(double)) : 0;
+  L.elmat = o; o += op->P == 2 ? align256((size_t)op->E * 300 * sizeof(double)) : 0;
   const size_t nq = (size_t)op->tiles * op->NQ;
   if (!op->fine) {
     L.geo = o; o += align256(nq * NGEO * sizeof(double));
@@ -211,7 +211,7 @@ int hpmg_op_bind_workspace(hpmg_op op, void *ws, size_t bytes, void *stream) {
   op->csr_off = reinterpret_cast<int32_t *>(w + L.csr_off);
   op->csr_inc = reinterpret_cast<int32_t *>(w + L.csr_inc);
   op->evec = reinterpret_cast<double *>(w + L.evec);
-  op->elmat = (op->fine && op->P == 2) ? reinterpret_cast<double *>(w + L.elmat) : nullptr;
+  op->elmat = op->P == 2 ? reinterpret_cast<double *>(w + L.elmat) : nullptr;
   op->elmat_prec = -1;
   if (!op->fine) {
     op->geo = reinterpret_cast<double *>(w + L.geo);
@@ -447,14 +447,15 @@ int hpmg_op_assemble_elements(hpmg_op op, int precision, void *stream) {
   int st = check_ready(op, "assemble_elements");
   if (st) return st;
   if ((st = check_prec(precision, "assemble_elements"))) return st;
-  if (!op->fine || op->P != 2 || !op->elmat)
-    return fail(HPMG_ERR_UNSUPPORTED, "assemble_elements: only for coarse operators of order 1");
-  if (!op->fine->state_ready) return fail(HPMG_ERR_ARG, "assemble_elements: no stored linearisation");
-  if (precision == HPMG_F32 && !op->fine->state32_ready)
+  if (op->P != 2 || !op->elmat)
+    return fail(HPMG_ERR_UNSUPPORTED, "assemble_elements: only for operators of order 1");
+  const hpmg_op_s *src = op->fine ? op->fine : op;  // where the linearisation is stored
+  if (!src->state_ready) return fail(HPMG_ERR_ARG, "assemble_elements: no stored linearisation");
+  if (precision == HPMG_F32 && !src->state32_ready)
     return fail(HPMG_ERR_ARG, "assemble_elements: FP32 state not cast");
   HPMG_HIP(launch_elmat_build(*op, precision, S(stream)));
   op->elmat_prec = precision;
-  op->elmat_version = op->fine->state_version;
+  op->elmat_version = src->state_version;
   return HPMG_OK;
 }
 

@@ -2077,7 +2077,7 @@ hipError_t launch_vjp(const hpmg_op_s &op, int prec, int mode, const double *u, 
 }
 
 hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s) {
-  const hpmg_op_s &f = *op.fine;
+  const hpmg_op_s &f = op.fine ? *op.fine : op;  // the operator holding the linearisation
   const unsigned g = grid1d(op.E, ELB);
 #define X(q)                                                                                          \
   if (op.Q == q) {                                                                                    \

@@ -187,8 +187,8 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
   const double rtol2 = fixed > 0 ? -1.0 : rtol * rtol;
   // The assembled coarsest level (when its blocks match the current linearisation)
   // takes two launches per iteration; otherwise four.
-  const bool ell = !record && l + 1 == mg->lv.size() && mg->ell_ready &&
-                   mg->ell_version == mg->lv[0].op->state_version;
+  const hpmg_op_s *src = L.op->fine ? L.op->fine : L.op;  // holder of the level's linearisation
+  const bool ell = !record && l + 1 == mg->lv.size() && mg->ell_ready && mg->ell_version == src->state_version;
   const int64_t nn = L.n / 3;
   const int nb_pq = ell ? ell_pcg_blocks(nn, mg->ell_w) : (int)((nn + 255) / 256);
   int queued = 0, its = limit;
@@ -387,14 +387,15 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
   }
   Level &Lc = mg->lv.back();
   mg->ell_ready = false;
-  if (mg->prm.coarse_element_matrices && Lc.op->P == 2 && Lc.op->elmat) {
+  if (mg->prm.coarse_element_matrices && Lc.op->P == 2 && Lc.op->elmat && Lc.op->fine) {
+    const hpmg_op_s *src = Lc.op->fine;
     HPMG_HIP(launch_elmat_build(*Lc.op, prec, s));
     Lc.op->elmat_prec = prec;
-    Lc.op->elmat_version = fine->state_version;
+    Lc.op->elmat_version = src->state_version;
     if (mg->ell_w > 0) {
       HPMG_HIP(launch_ell_build(*Lc.op, prec, mg->ell_w, mg->ell_cols, mg->ell_vals, s));
       mg->ell_ready = true;
-      mg->ell_version = fine->state_version;
+      mg->ell_version = src->state_version;
     }
   }
   for (size_t l = 0; l + 1 < mg->lv.size(); ++l) {
@@ -537,6 +538,8 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
     L.redisc = l > 0 && redisc;
     mg->lv.push_back(L);
   }
+  // Galerkin order-1 coarsest level only: a rediscretised one on its own 2^3 Gauss points
+  // is cheaper matrix-free than as assembled blocks (measured)
   if (!redisc && params->coarse_element_matrices && mg->lv.back().op->P == 2) {
     const int st = build_ell_structure(mg);
     if (st) {

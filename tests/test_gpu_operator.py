@@ -301,6 +301,25 @@ def test_element_matrices_go_stale_with_the_state():
     assert rel(t2n(H.ops[1].jacobian(_dev(x), "f64")), Kc @ x.reshape(-1)) < TOL64
 
 
+@pytest.mark.parametrize("q", [2, 3])
+def test_element_matrices_of_a_standalone_order1_operator(q):
+    """Element matrices of an order-1 operator from its own linearisation (a rediscretised
+    coarse level): the apply from them equals the oracle's Jacobian on the same
+    quadrature, in FP64 and FP32."""
+    print_case("elmat_standalone", q=q)
+    faces = {"x0": (1, 1, 1), "y1": (0, 1, 0)}
+    m, H = _setup((3, 2, 2), 1, faces=faces, q=q)
+    d, mask, u, du = _oracle_problem(m, q, faces)
+    op = H.fine
+    op.residual(_dev(u), store_state=True)
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
+    op.assemble_elements("f64")
+    assert rel(t2n(op.jacobian(_dev(du), "f64")), y_ref) < TOL64
+    op.state_cast_f32()
+    op.assemble_elements("f32")
+    assert rel(t2n(op.jacobian(_dev(du).float(), "f32")), y_ref) < TOL32
+
+
 @pytest.mark.parametrize("p", [2, 4])
 def test_external_load_matches_oracle(p):
     """Body force and traction dead loads (Q2, Q4 on a 2 x 1 x 0.5 box, jittered,
