@@ -259,6 +259,8 @@ def main():
     ap.add_argument("--pmg-inclusions", action="store_true",
                     help="p-MG solve of the multiscale block: stiff inclusions, compression between roller faces "
                          "in 10 load steps")
+    ap.add_argument("--pmg-newton-only", action="store_true",
+                    help="only the Galerkin Newton solves (FP64 and mixed): no rediscretised or L-BFGS legs")
     ap.add_argument("--pmg-strain", type=float, default=0.15,
                     help="compressive strain of the multiscale block (0.15: the 16^3 block stays stable)")
     args = ap.parse_args()
@@ -275,9 +277,11 @@ def main():
     if args.pmg_only:
         if args.pmg_inclusions:
             res = pmg_solve(n=args.pmg_n, steps=10, total_disp=-args.pmg_strain, inclusions=True,
-                            monitor=args.pmg_monitor)
+                            monitor=args.pmg_monitor, lbfgs=not args.pmg_newton_only,
+                            rediscretize=not args.pmg_newton_only)
         else:
-            res = pmg_solve(n=args.pmg_n, monitor=args.pmg_monitor)
+            res = pmg_solve(n=args.pmg_n, monitor=args.pmg_monitor, lbfgs=not args.pmg_newton_only,
+                            rediscretize=not args.pmg_newton_only)
         print(json.dumps({"pmg_solve": res}))
         return
 
