@@ -47,6 +47,7 @@ def _oracle_vcycle(m, H, u, coarse_fixed, degree=3):
     (2, [2, 1], {"x0": (1, 1, 1)}),
     (2, [4, 2, 1], {"x0": (1, 1, 1), "x1": (1, 1, 1)}),
     ((3, 2, 2), [3, 1], {"x0": (1, 1, 1)}),
+    ((2, 1, 1), [2, 1], {"x0": (1, 1, 1)}),  # no node with 27 neighbours: general-width blocks
 ])
 def test_vcycle_matches_oracle(n, orders, faces):
     from paper_2204_01722_amd.binding import PMG
@@ -66,7 +67,7 @@ def test_vcycle_matches_oracle(n, orders, faces):
         assert rel(z, ref) < tol, (prec, rel(z, ref))
 
 
-@pytest.mark.parametrize("n,orders", [(3, [2, 1]), (2, [4, 2, 1])])
+@pytest.mark.parametrize("n,orders", [(3, [2, 1]), (2, [4, 2, 1]), ((4, 1, 1), [2, 1])])
 def test_vcycle_coarse_tolerance_matches_oracle(n, orders):
     """Coarse Jacobi-PCG to a relative tolerance (stopping test on the device, iterations
     queued in batches): the V-cycle and the coarse iteration count equal the oracle's,
@@ -80,7 +81,7 @@ def test_vcycle_coarse_tolerance_matches_oracle(n, orders):
     fr = 1.0 - H.masks[0].reshape(-1)
     rs = [inputs.random_vector(m.n_nodes, 23 + k).reshape(-1) * fr for k in range(3)]
     refs = [V(r) for r in rs]
-    assert min(V.coarse_its) > 4
+    assert min(V.coarse_its) > 2
     for elmat in (True, False):
         pmg = PMG(H.ops, precision="f64", coarse_rtol=1e-3, coarse_element_matrices=elmat)
         pmg.setup(H.seeds(7))
