@@ -57,6 +57,9 @@ constexpr int RED_BLOCKS = 512;  // fixed grid of the deterministic reductions
 // (10), completed iterations (11), r.r of the start (12); per-iteration alpha and beta
 // when recorded for the eigenvalue estimate (SC_ALPHA + k, SC_BETA + k, k < PCG_RECORD).
 constexpr int SC_STOP = 10, SC_COUNT = 11, SC_RR0 = 12;
+// Flexible CG (FP64, device scalars): p.q, r.r of the new residual, breakdown flag,
+// alpha, z.r_new and z.r_old of the Polak-Ribiere beta, r.z alternating (FCG_RZ + 0, 1).
+constexpr int FCG_PQ = 13, FCG_RR = 14, FCG_BRK = 15, FCG_ALPHA = 16, FCG_ZRN = 17, FCG_ZR = 18, FCG_RZ = 19;
 constexpr int PCG_RECORD = 64;
 constexpr int SC_ALPHA = 32, SC_BETA = SC_ALPHA + PCG_RECORD, SC_N = SC_BETA + PCG_RECORD;
 
@@ -125,6 +128,13 @@ hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, vo
 // not null), counts the iteration in sc[SC_COUNT] and sets the stop flag on breakdown
 // or when r.r <= rtol2 * sc[SC_RR0] (rtol2 < 0: never).
 hipError_t launch_pcg_begin(double *sc, hipStream_t s);
+// FCG steps on the slots above (FP64): update: alpha = r.z / p.q from the device
+// scalars (0 on a breakdown, p.q <= 0 or r.z not finite, which sets sc[FCG_BRK]),
+// x += alpha p, rn = r - alpha q, sc[FCG_RR] = rn.rn.  dir: beta = (z.rn - z.r) / r.z,
+// r.z <- z.rn, p = z + beta p.  r.z of iteration `it` is read from FCG_RZ + (it & 1).
+hipError_t launch_fcg_update(int64_t n, double *sc, int it, const double *p, const double *q, double *x,
+                             const double *r, double *rn, double *partial, hipStream_t s);
+hipError_t launch_fcg_dir(int64_t n, double *sc, int it, const double *z, double *p, hipStream_t s);
 // The iteration on an order-1 operator assembled into 3 x 3 blocks (sliced ELL, width W,
 // nn nodes): one launch replaces the element kernel, the fused assembly and dir2;
 // ell_pcg_blocks(nn, W) workgroups write pq_part.  nn = 0 runs only the stopping test

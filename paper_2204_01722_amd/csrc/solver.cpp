@@ -425,49 +425,43 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
            double *rel_out, hipStream_t s) {
   int st;
   const int64_t n = mg->lv[0].n;
+  double *sc = mg->scal;
   double *r = mg->fr, *rn = mg->fr2, *z = mg->fz, *p = mg->fp, *q = mg->fq;
   *its_out = 0;
   *rel_out = 0.0;
   HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, x, q, s));
   HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, b, -1.0, q, r, s));
-  HPMG_HIP(launch_dot(HPMG_F64, n, r, r, mg->red, mg->scal, s));
+  HPMG_HIP(launch_dot(HPMG_F64, n, r, r, mg->red, sc, s));
   if ((st = read_scalars(mg, 1, s))) return st;
   const double r0 = std::sqrt(mg->host[0]);
   if (r0 == 0.0) return HPMG_OK;
   if ((st = vcycle(mg, r, z, s))) return st;
-  HPMG_HIP(launch_dot(HPMG_F64, n, r, z, mg->red, mg->scal, s));
-  if ((st = read_scalars(mg, 1, s))) return st;
-  double rz = mg->host[0];
+  HPMG_HIP(launch_dot(HPMG_F64, n, r, z, mg->red, sc + FCG_RZ, s));
   HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, z, 0.0, z, p, s));
+  // alpha and beta are formed on the device from the dot products; the host reads the
+  // scalars once per iteration, for the convergence and breakdown tests.
   int its = 0;
   double rel = 1.0;
   while (its < maxit) {
     HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, p, q, s));
-    HPMG_HIP(launch_dot(HPMG_F64, n, p, q, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 1, s))) return st;
-    const double pq = mg->host[0];
-    if (!(pq > 0.0) || !std::isfinite(rz)) {
-      // Negative curvature (or a non-finite preconditioned residual): stop here.  The
-      // iterate so far is returned; before the first step the preconditioned residual is
-      // returned instead, so a caller can still search along a descent direction.
-      if (its == 0 && std::isfinite(rz)) HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0, z, 1.0, x, s));
+    HPMG_HIP(launch_dot(HPMG_F64, n, p, q, mg->red, sc + FCG_PQ, s));
+    HPMG_HIP(launch_fcg_update(n, sc, its, p, q, x, r, rn, mg->red, s));
+    if ((st = read_scalars(mg, FCG_RZ + 2, s))) return st;
+    if (mg->host[FCG_BRK] != 0.0) {
+      // Negative curvature (or a non-finite preconditioned residual): stop here, x as it
+      // was.  Before the first step the preconditioned residual is returned instead, so a
+      // caller can still search along a descent direction.
+      if (its == 0 && std::isfinite(mg->host[FCG_RZ])) HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0, z, 1.0, x, s));
       *its_out = its;
       *rel_out = rel;
       return fail(HPMG_ERR_BREAKDOWN, "fcg: p^T A p <= 0");
     }
-    const double alpha = rz / pq;
-    HPMG_HIP(launch_cg_update(HPMG_F64, n, alpha, p, q, x, r, rn, s));
     ++its;
-    HPMG_HIP(launch_dot(HPMG_F64, n, rn, rn, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 1, s))) return st;
-    rel = std::sqrt(mg->host[0]) / r0;
+    rel = std::sqrt(mg->host[FCG_RR]) / r0;
     if (rel <= rtol) break;
     if ((st = vcycle(mg, rn, z, s))) return st;
-    HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, mg->scal, s));
-    if ((st = read_scalars(mg, 2, s))) return st;
-    const double beta = (mg->host[0] - mg->host[1]) / rz;
-    rz = mg->host[0];
-    HPMG_HIP(launch_axpby(HPMG_F64, n, 1.0, z, beta, p, s));
+    HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));  // z.rn, z.r
+    HPMG_HIP(launch_fcg_dir(n, sc, its - 1, z, p, s));
     std::swap(r, rn);
   }
   *its_out = its;

@@ -301,6 +301,35 @@ __global__ __launch_bounds__(BS) void k_pcg_dir2(int64_t n, double *__restrict__
   GRID_STRIDE(i, n) { p[i] = z[i] + b * p[i]; }
 }
 
+__global__ __launch_bounds__(BS) void k_fcg_update(int64_t n, double *__restrict__ sc, int it,
+                                                   const double *__restrict__ p, const double *__restrict__ q,
+                                                   double *__restrict__ x, const double *__restrict__ r,
+                                                   double *__restrict__ rn, double *__restrict__ partial) {
+  const double pq = sc[FCG_PQ], rz = sc[FCG_RZ + (it & 1)];
+  const bool brk = !(pq > 0.0) || !isfinite(rz);
+  const double a = brk ? 0.0 : rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[FCG_BRK] = brk ? 1.0 : 0.0;
+    sc[FCG_ALPHA] = a;
+  }
+  double v[1] = {0.0};
+  GRID_STRIDE(i, n) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    rn[i] = ri;
+    v[0] += ri * ri;
+  }
+  block_store<1>(v, partial);
+}
+
+__global__ __launch_bounds__(BS) void k_fcg_dir(int64_t n, double *__restrict__ sc, int it,
+                                                const double *__restrict__ z, double *__restrict__ p) {
+  const double zrn = sc[FCG_ZRN], rz = sc[FCG_RZ + (it & 1)];
+  const double beta = (zrn - sc[FCG_ZR]) / rz;
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc[FCG_RZ + ((it + 1) & 1)] = zrn;
+  GRID_STRIDE(i, n) { p[i] = z[i] + beta * p[i]; }
+}
+
 __device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
@@ -389,6 +418,18 @@ __global__ __launch_bounds__(BS) void k_ell_pcg_apply(int64_t nn, int W, const i
 }
 
 }  // namespace
+
+hipError_t launch_fcg_update(int64_t n, double *sc, int it, const double *p, const double *q, double *x,
+                             const double *r, double *rn, double *partial, hipStream_t s) {
+  k_fcg_update<<<RED_BLOCKS, BS, 0, s>>>(n, sc, it, p, q, x, r, rn, partial);
+  k_final<<<1, RED_BLOCKS, 0, s>>>(partial, RED_BLOCKS, 1, sc + FCG_RR);
+  return hipGetLastError();
+}
+
+hipError_t launch_fcg_dir(int64_t n, double *sc, int it, const double *z, double *p, hipStream_t s) {
+  k_fcg_dir<<<grid_for(n), BS, 0, s>>>(n, sc, it, z, p);
+  return hipGetLastError();
+}
 
 hipError_t launch_pcg_begin(double *sc, hipStream_t s) {
   k_pcg_begin<<<1, 64, 0, s>>>(sc);
