@@ -247,6 +247,44 @@ def fcg(A, prec, b, rtol=1e-8, maxit=500, x0=None):
     return x, its, rel
 
 
+def fcg_truncated(A, prec, b, rtol=1e-8, maxit=500):
+    """Flexible CG as ``fcg`` from x0 = 0, stopped at a direction of non-positive
+    curvature (p^T A p <= 0, possible when the Newton tangent is indefinite): the iterate
+    reached so far is returned, or the preconditioned residual when it happens before the
+    first step, so that a Newton step can still move along a descent direction (the
+    truncated-Newton treatment of negative curvature).  Returns
+    ``x, its, final_relres, broke``."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    r0 = np.linalg.norm(r)
+    if r0 == 0.0:
+        return x, 0, 0.0, False
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    its, rel = 0, 1.0
+    while its < maxit:
+        q = A @ p
+        pq = p @ q
+        if not (pq > 0.0) or not np.isfinite(rz):
+            if its == 0 and np.isfinite(rz):
+                x = x + z
+            return x, its, rel, True
+        a = rz / pq
+        x += a * p
+        r_new = r - a * q
+        its += 1
+        rel = np.linalg.norm(r_new) / r0
+        if rel <= rtol:
+            break
+        z = prec(r_new)
+        beta = (z @ (r_new - r)) / rz
+        rz = r_new @ z
+        p = z + beta * p
+        r = r_new
+    return x, its, rel, False
+
+
 def line_search_cp(resid, u, du):
     """Critical-point line search: one secant step on ``g(a) = F(u + a du)^T du``."""
     g0 = resid(u).reshape(-1) @ du.reshape(-1)

@@ -98,12 +98,12 @@ def test_lambda_max_estimate_bounds():
     assert est >= 0.8 * true
 
 
-def _two_level(n=2, pf=2, pc=1, coarse_fixed=None, coarse_rtol=1e-3, degree=3):
+def _two_level(n=2, pf=2, pc=1, coarse_fixed=None, coarse_rtol=1e-3, degree=3, amplitude=0.05):
     mf, mc, Pm = _levels(n, pf, pc)
     d = fem.make_disc(mf.coords, mf.elem_nodes, mf.P)
     maskf = inputs.face_mask(mf, {"x0": (1, 1, 1)})
     maskc = inputs.face_mask(mc, {"x0": (1, 1, 1)})
-    u = inputs.config1_u(mf, amplitude=0.05)
+    u = inputs.config1_u(mf, amplitude=amplitude)
     K = fem.tangent_matrix(d, u, MU, LAM)
     seeds = [inputs.rough_seed(mf.n_nodes, maskf, 7)]
     V = mg.VCycle(K, [Pm], [maskf, maskc], seeds, degree=degree, coarse_rtol=coarse_rtol,
@@ -131,6 +131,34 @@ def test_fcg_matches_direct_solve():
     assert rel <= 1e-10
     assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
     assert its < 100
+
+
+def test_fcg_truncated_solves_spd_systems_like_a_direct_solve():
+    # the tangent at the reference configuration (linear elasticity) is positive definite
+    mf, maskf, V = _two_level(amplitude=0.0)
+    A = V.ops[0]
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0.0
+    rng = np.random.default_rng(2)
+    b = rng.normal(size=A.shape[0]) * (1.0 - maskf.reshape(-1))
+    x, its, rel, broke = mg.fcg_truncated(A, V, b, rtol=1e-10, maxit=200)
+    xs = spla.spsolve(A.tocsc(), b)
+    assert not broke and rel <= 1e-10
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_fcg_truncated_stops_at_negative_curvature():
+    """Closed forms with the identity preconditioner.  A = diag(1, -3), b = (1, 1):
+    p0^T A p0 = -2 before any step, so the preconditioned residual b comes back.
+    A = diag(2, 1, -3), b = (1, 1, 1/2): the first step is the CG step
+    x1 = (b.b / b^T A b) b = b (b.b = b^T A b = 9/4), the second direction has
+    p1^T A p1 < 0, so x1 comes back after one iteration."""
+    ident = lambda r: r.copy()
+    x, its, _, broke = mg.fcg_truncated(np.diag([1.0, -3.0]), ident, np.array([1.0, 1.0]))
+    assert broke and its == 0
+    np.testing.assert_array_equal(x, [1.0, 1.0])
+    x, its, _, broke = mg.fcg_truncated(np.diag([2.0, 1.0, -3.0]), ident, np.array([1.0, 1.0, 0.5]))
+    assert broke and its == 1
+    np.testing.assert_allclose(x, [1.0, 1.0, 0.5], rtol=0, atol=1e-15)
 
 
 def _uniaxial_stretch(lx, mu, lam):
