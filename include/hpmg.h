@@ -282,9 +282,11 @@ int hpmg_mg_info(hpmg_mg mg, int level, double *lambda_max, int *last_coarse_its
 int hpmg_mg_stats(hpmg_mg mg, int64_t *out);
 
 /* a14: flexible CG (FP64) on the fine operator, preconditioned by one V-cycle of
- * `mg` (or Jacobi with the fine FP64 diagonal if mg is NULL and diag given).
- * Solves J x = b from the x passed in; stops at ||b - Jx|| <= rtol ||b - J x0||.
- * Synchronises once per iteration. */
+ * `mg`.  Solves J x = b from the x passed in; stops at ||b - Jx|| <= rtol ||b - J x0||.
+ * A direction of non-positive curvature (p^T J p <= 0, possible when the tangent is
+ * indefinite) stops it with HPMG_ERR_BREAKDOWN and x at the iterate reached (x plus the
+ * preconditioned residual if it happens before the first step).  Step lengths are
+ * formed on the device; synchronises once per iteration. */
 int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double rtol, int maxit,
                    int *its, double *relres, void *stream);
 

@@ -113,6 +113,30 @@ def test_fcg_matches_direct_solve(prec):
     print(f"[fcg] precision={prec} iterations={its}", flush=True)
 
 
+@pytest.mark.parametrize("amplitude,its_ref", [(0.1, 0), (0.05, 1)])
+def test_fcg_negative_curvature_matches_oracle(amplitude, its_ref):
+    """An indefinite tangent (a non-equilibrium field between clamped faces): FCG stops
+    at the first direction of non-positive curvature with the oracle's iterate (the
+    preconditioned residual when that happens before the first step)."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG, HpmgError
+    print_case("fcg_negative_curvature", amplitude=amplitude)
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m, H, u = _build(3, [2, 1], faces, amplitude=amplitude)
+    V = _oracle_vcycle(m, H, u, coarse_fixed=8)
+    fr = 1.0 - H.masks[0].reshape(-1)
+    b = inputs.random_vector(m.n_nodes, 22).reshape(-1) * fr
+    x_ref, its, _, broke = omg.fcg_truncated(V.ops[0], V, b, rtol=1e-10, maxit=100)
+    assert broke and its == its_ref
+    pmg = PMG(H.ops, precision="f64", coarse_fixed_its=8)
+    pmg.setup(H.seeds(7))
+    x = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(HpmgError) as err:
+        pmg.fcg(_dev(b.reshape(-1, 3)), x=x, rtol=1e-10, maxit=100)
+    assert err.value.status == 8  # HPMG_ERR_BREAKDOWN
+    assert rel(t2n(x), x_ref) < 1e-10
+
+
 def _uniaxial_stretch(lx, mu, lam):
     t = 1.0
     for _ in range(50):
