@@ -20,7 +20,9 @@ Readings taken where the paper is silent:
   degree counts operator applications (first one on the initial residual);
 * the coarsest level is solved by Jacobi-PCG (relative 2-norm tolerance, ``x0 = 0``),
   optionally for a fixed number of iterations;
-* the outer solver is flexible CG with the Polak-Ribiere form of beta;
+* the outer solver is flexible CG with the Polak-Ribiere form of beta; inside Newton it
+  stops at a direction of non-positive curvature and returns the iterate so far (the
+  preconditioned residual before the first step), as truncated Newton does;
 * Newton stops on the 2-norm of the residual relative to the load step's first one;
   the line search takes one secant step for ``F(u + a du)^T du = 0`` from ``a = 0, 1``
   and clips ``a`` to ``[0.1, 1.5]`` (``a = 1`` if the secant slope is not positive);
