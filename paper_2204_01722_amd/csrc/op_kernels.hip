@@ -677,9 +677,10 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   constexpr int NH = MODE == 2 ? 16 : MODE == 3 ? 19 : 9;
   if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
-  // Per element: v [3][Q^3] (du, then its values at the points, then the nodal result)
-  // and G [3][3][Q^3] (gradient, then the flux).
-  constexpr int ELS = 12 * Q3;
+  // Per element: v [3][Q^3] (du, then its values at the points, then the z-derivative
+  // G[c][2] and the z-flux in place, then the nodal result) and G [3][2][Q^3] (the x- and
+  // y-derivatives, then the x- and y-flux): 9 Q^3 scalars, so that more tiles fit in LDS.
+  constexpr int ELS = 9 * Q3;
   __shared__ T lds[ET * ELS];
   const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
   const int64_t tile = xcd_tile();
@@ -729,11 +730,12 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   __syncthreads();
   line_stage<T, Q, 2, P, Q, false, Q, Q, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  // Collocated derivative in the three directions: G[c][k] = D_k v[c].
+  // Collocated derivative in the three directions: G[c][k] = D_k v[c] for k = 0, 1 into
+  // G, then (once every x and y line has read v) D_z v[c] in place over v[c].
   {
-    constexpr int TASKS = 9 * Q2;
+    constexpr int TASKS = 6 * Q2;
     for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 3, k = ck % 3, ln = r % Q2;
+      const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 2, k = ck % 2, ln = r % Q2;
       if (te >= nel) break;
       const T *src = lds + te * ELS + c * Q3;
       T *dst = lds + te * ELS + (3 + ck) * Q3;
@@ -745,31 +747,42 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
         line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
         for (int i = 0; i < Q; ++i) dst[b0 + i] = y[i];
-      } else if (k == 1) {
+      } else {
         const int b1 = line_base<Q, 1, Q>(ln);
 #pragma unroll
         for (int i = 0; i < Q; ++i) x[i] = src[b1 + i * Q];
         line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
         for (int i = 0; i < Q; ++i) dst[b1 + i * Q] = y[i];
-      } else {
-        const int b2 = line_base<Q, 2, Q>(ln);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = src[b2 + i * Q2];
-        line_apply<T, Q, Q, false>(tD, x, y);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dst[b2 + i * Q2] = y[i];
       }
     }
   }
   __syncthreads();
-  // Quadrature function, one thread per point, flux written over the gradient.
+  {
+    constexpr int TASKS = 3 * Q2;
+    for (int t = tq; t < ET * TASKS; t += NT) {
+      const int te = t / TASKS, r = t % TASKS, c = r / Q2, ln = r % Q2;
+      if (te >= nel) break;
+      T *p = lds + te * ELS + c * Q3 + line_base<Q, 2, Q>(ln);
+      T x[Q], y[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i) x[i] = p[i * Q2];
+      line_apply<T, Q, Q, false>(tD, x, y);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) p[i * Q2] = y[i];
+    }
+  }
+  __syncthreads();
+  // Quadrature function, one thread per point, flux written over the gradient
+  // (components k = 0, 1 in G, k = 2 in v).
   if (live) {
     T Gq[3][3], f[3][3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) Gq[c][k] = G[(c * 3 + k) * Q3 + q];
+    for (int c = 0; c < 3; ++c) {
+      Gq[c][0] = G[(c * 2) * Q3 + q];
+      Gq[c][1] = G[(c * 2 + 1) * Q3 + q];
+      Gq[c][2] = v[c * Q3 + q];
+    }
     if constexpr (MODE == 0) {
       T A[3][3], tau[6];
 #pragma unroll
@@ -801,9 +814,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
       jacobian_qf_initial<MODE == 2>(Gq, gv, hv, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), f);
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) G[(i * 3 + k) * Q3 + q] = f[i][k];
+    for (int i = 0; i < 3; ++i) {
+      G[(i * 2) * Q3 + q] = f[i][0];
+      G[(i * 2 + 1) * Q3 + q] = f[i][1];
+      v[i * Q3 + q] = f[i][2];
+    }
   }
   __syncthreads();
   // Transposed derivative, x and y directions in place on the flux arrays.
@@ -812,7 +827,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     for (int t = tq; t < ET * TASKS; t += NT) {
       const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 2, k = ck % 2, ln = r % Q2;
       if (te >= nel) break;
-      T *p = lds + te * ELS + (3 + c * 3 + k) * Q3;
+      T *p = lds + te * ELS + (3 + c * 2 + k) * Q3;
       T x[Q], y[Q];
       if (k == 0) {
         const int b0 = line_base<Q, 0, Q>(ln);
@@ -833,22 +848,23 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   }
   __syncthreads();
   // z direction: h = D_z^T f_z + (x and y parts), then the first transposed
-  // interpolation stage (B_z^T, Q -> P) in registers; the result goes to v.
+  // interpolation stage (B_z^T, Q -> P) in registers; the result goes to v, over the
+  // z-flux line it was formed from.
   {
     constexpr int TASKS = 3 * Q2;
     for (int t = tq; t < ET * TASKS; t += NT) {
       const int te = t / TASKS, r = t % TASKS, c = r / Q2, ln = r % Q2;
       if (te >= nel) break;
       const int b2 = line_base<Q, 2, Q>(ln);
-      const T *f = lds + te * ELS + (3 + c * 3) * Q3 + b2;
+      const T *fxy = lds + te * ELS + (3 + c * 2) * Q3 + b2;
+      T *o = lds + te * ELS + c * Q3 + b2;
       T x[Q], y[Q], z[P];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) x[i] = f[2 * Q3 + i * Q2];
+      for (int i = 0; i < Q; ++i) x[i] = o[i * Q2];
       line_apply<T, Q, Q, true>(tD, x, y);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) y[i] += f[i * Q2] + f[Q3 + i * Q2];
+      for (int i = 0; i < Q; ++i) y[i] += fxy[i * Q2] + fxy[Q3 + i * Q2];
       line_apply<T, Q, P, true>(tB, y, z);
-      T *o = lds + te * ELS + c * Q3 + b2;
 #pragma unroll
       for (int i = 0; i < P; ++i) o[i * Q2] = z[i];
     }
