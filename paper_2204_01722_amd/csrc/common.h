@@ -137,9 +137,9 @@ hipError_t launch_fcg_update(int64_t n, double *sc, int it, const double *p, con
 hipError_t launch_fcg_dir(int64_t n, double *sc, int it, const double *z, double *p, hipStream_t s);
 // The iteration on an order-1 operator assembled into 3 x 3 blocks (sliced ELL, width W,
 // nn nodes): one launch replaces the element kernel, the fused assembly and dir2;
-// ell_pcg_blocks(nn, W) workgroups write pq_part.  nn = 0 runs only the stopping test
-// of the iteration before `it` (to close a batch).
-int ell_pcg_blocks(int64_t nn, int W);
+// ell_pcg_blocks(nn) workgroups write pq_part.  nn = 0 runs only the stopping test of
+// the iteration before `it` (to close a batch).
+int ell_pcg_blocks(int64_t nn);
 hipError_t launch_ell_pcg_apply(int prec, int64_t nn, int W, const int32_t *cols, const void *vals, const void *z,
                                 const void *p_old, void *p_new, void *y, double *sc, const double *partial, int it,
                                 double rtol2, double *pq_part, hipStream_t s);

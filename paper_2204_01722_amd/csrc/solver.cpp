@@ -79,7 +79,7 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   mg->scal = reinterpret_cast<double *>(take(SC_N * sizeof(double)));
   int64_t nmax = 0;
   for (const Level &L : mg->lv) nmax = std::max<int64_t>(nmax, L.n / 3);
-  const int64_t nb_pq = std::max<int64_t>((nmax + 255) / 256, ell_pcg_blocks(mg->lv.back().n / 3, mg->ell_w));
+  const int64_t nb_pq = std::max<int64_t>((nmax + 255) / 256, ell_pcg_blocks(mg->lv.back().n / 3));
   mg->pq_part = reinterpret_cast<double *>(take((size_t)(nb_pq + 1) * sizeof(double)));
   if (mg->ell_w > 0) {
     Level &C = mg->lv.back();
@@ -190,7 +190,7 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
   const hpmg_op_s *src = L.op->fine ? L.op->fine : L.op;  // holder of the level's linearisation
   const bool ell = !record && l + 1 == mg->lv.size() && mg->ell_ready && mg->ell_version == src->state_version;
   const int64_t nn = L.n / 3;
-  const int nb_pq = ell ? ell_pcg_blocks(nn, mg->ell_w) : (int)((nn + 255) / 256);
+  const int nb_pq = ell ? ell_pcg_blocks(nn) : (int)((nn + 255) / 256);
   int queued = 0, its = limit;
   int batch = fixed > 0 ? limit : std::max(check, predict), grow = check;
   while (queued < limit) {

@@ -436,15 +436,12 @@ hipError_t launch_pcg_begin(double *sc, hipStream_t s) {
   return hipGetLastError();
 }
 
-int ell_pcg_blocks(int64_t nn, int W) {
-  (void)W;
-  return (int)((3 * nn + BS - 1) / BS);
-}
+int ell_pcg_blocks(int64_t nn) { return (int)((3 * nn + BS - 1) / BS); }
 
 hipError_t launch_ell_pcg_apply(int prec, int64_t nn, int W, const int32_t *cols, const void *vals, const void *z,
                                 const void *p_old, void *p_new, void *y, double *sc, const double *partial, int it,
                                 double rtol2, double *pq_part, hipStream_t s) {
-  const unsigned g = nn > 0 ? (unsigned)ell_pcg_blocks(nn, W) : 1u;
+  const unsigned g = nn > 0 ? (unsigned)ell_pcg_blocks(nn) : 1u;
 #define ELL_LAUNCH(TT, WC)                                                                                    \
   k_ell_pcg_apply<TT, WC><<<g, BS, 0, s>>>(nn, W, cols, (const TT *)vals, (const TT *)z, (const TT *)p_old,    \
                                            (TT *)p_new, (TT *)y, sc, partial, it, rtol2, pq_part)
