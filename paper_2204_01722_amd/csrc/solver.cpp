@@ -169,7 +169,7 @@ double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &
 // at once), so the host queues iterations in batches and reads the scalars once per
 // batch: first `predict` iterations (the previous solve's count), then batches that
 // double from `check`.  With alphas and betas given, the CG coefficients are read back
-// (eigenvalue estimate; fixed <= PCG_RECORD).
+// (eigenvalue estimate; fixed <= PCG_RECORD) and the iterate is not formed.
 int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fixed, int predict, int check,
                hipStream_t s, int *its_out, std::vector<double> *alphas = nullptr,
                std::vector<double> *betas = nullptr) {
@@ -209,8 +209,8 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
       // Element kernel, assembly fused with p.Ap, the update (alpha from the p.Ap
       // partials) and the direction (beta from the r.z partials).
       HPMG_HIP(launch_jacobian_dot(*L.op, prec, L.d, L.t, mg->pq_part, sc + SC_STOP, s));
-      HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, L.x, L.r, L.dinv, L.z,
-                                  mg->red, record ? sc + SC_ALPHA + queued : nullptr, s));
+      HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, L.d, L.t, record ? nullptr : L.x,
+                                  L.r, L.dinv, L.z, mg->red, record ? sc + SC_ALPHA + queued : nullptr, s));
       HPMG_HIP(launch_pcg_dir2(prec, L.n, sc, parity, mg->red, L.z, L.d, rtol2,
                                record ? sc + SC_BETA + queued : nullptr, s));
     }

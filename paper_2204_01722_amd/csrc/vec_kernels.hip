@@ -241,7 +241,8 @@ __global__ void k_pcg_begin(double *__restrict__ sc) {
   }
 }
 
-// update2: alpha = rz / pq, x += alpha p, r -= alpha q, z = D^-1 r, partials of r.z, r.r.
+// update2: alpha = rz / pq, x += alpha p (skipped when x is null: the eigenvalue estimate
+// needs only the coefficients), r -= alpha q, z = D^-1 r, partials of r.z, r.r.
 template <typename T>
 __global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restrict__ sc, int parity, int nb_pq,
                                                     const double *__restrict__ pq_partial,
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(BS) void k_pcg_update2(int64_t n, double *__restric
   const T a = (T)alpha;
   double v[2] = {0.0, 0.0};
   GRID_STRIDE(i, n) {
-    x[i] += a * p[i];
+    if (x) x[i] += a * p[i];
     const T ri = r[i] - a * q[i];
     r[i] = ri;
     const T zi = dinv[i] * ri;
