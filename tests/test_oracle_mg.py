@@ -1,7 +1,9 @@
 """Pins of the oracle's multigrid pieces and solver drivers (CPU only): interpolation of
 affine fields, the exact-Galerkin identity of coarse operators built on the fine
 quadrature, the closed-form Chebyshev error polynomial, Ritz bounds of the eigenvalue
-estimate, flexible CG against a direct solve, symmetry of the V-cycle, the homogeneous
+estimate and its exact pins (the tridiagonal read from the CG coefficients has the whole
+known spectrum after a full-dimension run, and equals plain Lanczos on the Jacobi-scaled
+matrix entry by entry), flexible CG against a direct solve, symmetry of the V-cycle, the homogeneous
 uniaxial-stretch solution of the Newton driver, and L-BFGS (its iterates equal those of
 CG on a quadratic with exact line search, one step with the exact inverse Hessian, the
 Newton answer on a Neo-Hookean problem)."""
@@ -96,6 +98,64 @@ def test_lambda_max_estimate_bounds():
     true = np.linalg.eigvalsh(S).max()
     assert est <= true * (1 + 1e-12)
     assert est >= 0.8 * true
+
+
+def _spd_with_spectrum(lams, seed):
+    """A = D^{1/2} S D^{1/2} with S = V diag(lams) V^T (V a seeded random orthogonal
+    matrix) and a seeded positive diagonal D: D^{-1} A is similar to S, so the spectrum
+    of the Jacobi-preconditioned operator is exactly ``lams``."""
+    rng = np.random.default_rng(seed)
+    n = len(lams)
+    V, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    S = V @ np.diag(lams) @ V.T
+    d = rng.uniform(0.5, 3.0, size=n)
+    A = np.sqrt(d)[:, None] * S * np.sqrt(d)[None, :]
+    return 0.5 * (A + A.T), d, rng.normal(size=n)
+
+
+def _plain_lanczos(S, w, k):
+    """Textbook symmetric Lanczos on S from w / ||w||, with full reorthogonalisation;
+    returns the k x k tridiagonal (diagonal a_j = v_j^T S v_j, off-diagonal b_j =
+    ||u_j||).  Independent of the CG recurrence."""
+    n = len(w)
+    Vs = np.zeros((n, k + 1))
+    Vs[:, 0] = w / np.linalg.norm(w)
+    a, b = np.zeros(k), np.zeros(k)
+    for j in range(k):
+        u = S @ Vs[:, j]
+        a[j] = Vs[:, j] @ u
+        u -= Vs[:, : j + 1] @ (Vs[:, : j + 1].T @ u)
+        u -= Vs[:, : j + 1] @ (Vs[:, : j + 1].T @ u)
+        b[j] = np.linalg.norm(u)
+        if j + 1 < k:
+            Vs[:, j + 1] = u / b[j]
+    return np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+
+
+def test_lanczos_tridiagonal_full_dimension_spectrum():
+    """Section III-A: the eigenvalue estimate reads the Lanczos tridiagonal from the CG
+    coefficients.  Run for the full dimension, its eigenvalues are the whole spectrum of
+    D^{-1} A (known here by construction) up to rounding."""
+    lams = np.array([0.3, 0.7, 1.1, 1.9, 2.6, 3.4, 5.0])
+    A, d, b = _spd_with_spectrum(lams, 11)
+    _, its, al, be = mg.pcg_jacobi(A, 1.0 / d, b, fixed_its=len(lams))
+    assert its == len(lams)
+    T = mg.lanczos_tridiagonal(al, be[: len(al) - 1])
+    np.testing.assert_allclose(np.linalg.eigvalsh(T), lams, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+def test_lanczos_tridiagonal_equals_plain_lanczos(k):
+    """Entry by entry, the tridiagonal built from k Jacobi-PCG coefficients equals plain
+    Lanczos on D^{-1/2} A D^{-1/2} started from D^{-1/2} b (off-diagonal signs are
+    immaterial: compared in absolute value)."""
+    lams = np.linspace(0.5, 4.0, 9) ** 1.3
+    A, d, b = _spd_with_spectrum(lams, 5)
+    _, _, al, be = mg.pcg_jacobi(A, 1.0 / d, b, fixed_its=k)
+    T = mg.lanczos_tridiagonal(al, be[: k - 1])
+    S = A / np.sqrt(d)[:, None] / np.sqrt(d)[None, :]
+    T_ref = _plain_lanczos(S, b / np.sqrt(d), k)
+    np.testing.assert_allclose(np.abs(T), np.abs(T_ref), rtol=1e-11, atol=1e-12)
 
 
 def _two_level(n=2, pf=2, pc=1, coarse_fixed=None, coarse_rtol=1e-3, degree=3, amplitude=0.05):
