@@ -106,13 +106,18 @@ def j_minus_1(H):
 
 
 def piola(H, mu, lam):
-    """First Piola stress of the compressible Neo-Hookean model; ``mu``, ``lam``
-    broadcast against the leading axes of ``H``."""
+    """First Piola stress ``P = mu (F - F^-T) + lambda log J F^-T`` of the compressible
+    Neo-Hookean model; ``mu``, ``lam`` broadcast against the leading axes of ``H``.
+
+    ``F - F^-T`` is formed as ``H + H^T F^-T`` (from ``F^-1 = I - F^-1 H``), so the
+    identities cancel analytically and small strains keep full relative accuracy, as
+    the Kirchhoff stress written with ``e`` in terms of ``grad u`` does (Section II-A)."""
     F = np.eye(3) + H
     Finv = np.linalg.inv(F)
     FinvT = np.swapaxes(Finv, -1, -2)
     logJ = np.log1p(j_minus_1(H))
-    return mu[..., None, None] * (F - FinvT) + (lam * logJ)[..., None, None] * FinvT
+    F_minus_FinvT = H + np.swapaxes(H, -1, -2) @ FinvT
+    return mu[..., None, None] * F_minus_FinvT + (lam * logJ)[..., None, None] * FinvT
 
 
 def tangent(H, mu, lam):

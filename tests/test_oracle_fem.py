@@ -73,6 +73,29 @@ def test_j_minus_1_against_50_digits():
     assert worst_j < 1e-13 and worst_l < 1e-13
 
 
+def test_piola_against_50_digits():
+    """The first Piola stress at strains from 1e-10 to 0.3 against mu (F - F^-T) +
+    lambda log J F^-T evaluated with 50-digit arithmetic: relative accuracy 1e-13 (a
+    form that subtracts I from F and from F^-T directly loses about |H|^-1 ulps)."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 50
+    rng = np.random.default_rng(12)
+    worst = 0.0
+    for scale in (1e-10, 1e-7, 1e-4, 1e-2, 0.3):
+        H = rng.normal(0, scale, (60, 3, 3))
+        H = H[np.linalg.det(np.eye(3) + H) > 0.1]
+        P = fem.piola(H, np.full(H.shape[0], MU), np.full(H.shape[0], LAM))
+        for k in range(H.shape[0]):
+            F = mpmath.matrix([[mpmath.mpf(float(H[k, i, j])) + (1 if i == j else 0)
+                                for j in range(3)] for i in range(3)])
+            FiT = (F ** -1).T
+            ex = MU * (F - FiT) + LAM * mpmath.log(mpmath.det(F)) * FiT
+            exn = mpmath.mnorm(ex, 1)
+            err = mpmath.mnorm(mpmath.matrix(P[k].tolist()) - ex, 1)
+            worst = max(worst, float(err / exn))
+    assert worst < 1e-13, worst
+
+
 def test_zero_displacement_zero_residual():
     m, d = _disc(2, 2)
     assert np.all(fem.residual(d, np.zeros((m.n_nodes, 3)), MU, LAM) == 0.0)
