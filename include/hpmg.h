@@ -118,6 +118,11 @@ int hpmg_op_bind_workspace(hpmg_op op, void *workspace, size_t bytes, void *stre
 /* info[0..7] = P, Q, n_elem, n_nodes, elements per tile, tiles, threads per block,
  * quadrature-array stride per field. */
 int hpmg_op_info(hpmg_op op, int64_t *info);
+/* Version of the stored linearisation that `op` applies (the fine operator's, for a
+ * coarse operator that shares it): a counter bumped by every call that overwrites it
+ * (hpmg_residual with store_state, multigrid setups and the Newton and L-BFGS drivers).
+ * Lets a caller detect that the state it linearised at has since been replaced. */
+int hpmg_op_state_version(hpmg_op op, uint64_t *version);
 /* Reads and clears the device flag word (synchronises `stream`). */
 int hpmg_op_query_flags(hpmg_op op, void *stream, unsigned *flags);
 
@@ -302,7 +307,10 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
  * is halved (at most 6 times).  A load increment whose Newton solve fails (iteration
  * limit, no admissible step, no descent direction) is retried from the previous
  * converged state in halves, at most 6 times in a row; after a converged increment the
- * increment doubles again up to the full step.  Statistics (host):
+ * increment doubles again up to the full step.  When the whole solve has spent
+ * max_total_newton Newton or max_total_krylov FCG iterations it stops with
+ * HPMG_ERR_NOT_CONVERGED and u at the last converged load level, so a solve that
+ * stalls returns in bounded time.  Statistics (host):
  *   stats[0] = total Newton iterations, stats[1] = total FCG iterations,
  *   stats[2] = final relative residual of the last increment, stats[3] = halvings,
  *   stats[4 + k] = Newton iterations spent in load step k (k < n_steps, at most 60). */
@@ -314,6 +322,8 @@ typedef struct {
   int line_search;  /* 1: critical-point secant step, clipped to [0.1, 1.5] */
   int monitor;      /* (0) 1: one line per Newton iteration on stderr: load, iteration,
                        relative residual, FCG iterations and outcome, step length */
+  int max_total_newton; /* (200) Newton iterations of the whole solve, retries included */
+  int max_total_krylov; /* (20000) FCG iterations of the whole solve, retries included */
 } hpmg_newton_params;
 void hpmg_newton_default_params(hpmg_newton_params *p);
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext,

@@ -4,7 +4,10 @@ Forward runs the fused residual kernel; backward runs the hand-written adjoint k
 (the transpose of the pointwise Jacobian map, scattered through E^T B^T), returning the
 cotangent of the displacement and of the per-element Lame parameters.  In "recompute"
 mode the backward rebuilds the linearisation from the saved displacement instead of
-reading the stored one, trading flops for memory.
+reading the stored one, trading flops for memory.  A "stored" backward checks that the
+operator still holds the linearisation its forward stored (another forward, a solve or
+a multigrid setup on the same operator replaces it); if not, it recomputes the
+linearisation from the saved displacement instead.
 """
 from __future__ import annotations
 
@@ -32,6 +35,7 @@ class NeoHookeanResidual(torch.autograd.Function):
         if mode == "stored" and precision == "f32":
             op.state_cast_f32()
         ctx.op, ctx.mode, ctx.precision = op, mode, precision
+        ctx.state_version = op.state_version() if mode == "stored" else None
         ctx.save_for_backward(ud, mu_e, lam_e)
         return r
 
@@ -41,5 +45,8 @@ class NeoHookeanResidual(torch.autograd.Function):
         op = ctx.op
         op.set_material(0.0, 0.0, mu_e, lam_e)
         wt = torch.float64 if ctx.precision == "f64" else torch.float32
-        ub, mub, lamb = op.residual_vjp(u, r_bar.contiguous().to(wt), mode=ctx.mode, precision=ctx.precision)
+        mode = ctx.mode
+        if mode == "stored" and op.state_version() != ctx.state_version:
+            mode = "recompute"  # the stored linearisation is no longer this forward's
+        ub, mub, lamb = op.residual_vjp(u, r_bar.contiguous().to(wt), mode=mode, precision=ctx.precision)
         return ub.to(torch.float64), mub, lamb, None, None, None

@@ -41,7 +41,8 @@ class MGParams(C.Structure):
 
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_newton", C.c_int), ("lin_rtol", C.c_double),
-                ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int)]
+                ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int),
+                ("max_total_newton", C.c_int), ("max_total_krylov", C.c_int)]
 
 
 class LbfgsParams(C.Structure):
@@ -64,6 +65,7 @@ _SIGS = {
     "hpmg_op_bind_workspace": ([_VP, _VP, C.c_size_t, _VP], _I),
     "hpmg_op_info": ([_VP, _VP], _I),
     "hpmg_op_query_flags": ([_VP, _VP, C.POINTER(C.c_uint)], _I),
+    "hpmg_op_state_version": ([_VP, C.POINTER(C.c_uint64)], _I),
     "hpmg_qdata_setup": ([_VP, _VP, _VP], _I),
     "hpmg_qdata_export": ([_VP, _VP, _VP], _I),
     "hpmg_residual": ([_VP, _VP, _VP, _I, _VP], _I),
@@ -135,6 +137,23 @@ def _p(t):
             raise ValueError("contiguous tensor expected")
         return C.c_void_p(t.data_ptr())
     return t
+
+
+def _vec(v, n_nodes, dtype, device, what):
+    """Checks an L-vector before its pointer reaches the library, which reads and writes
+    exactly ``3 * n_nodes`` entries of ``dtype``: a wrong dtype, size, device or layout
+    raises here instead of touching memory outside the tensor."""
+    if not isinstance(v, torch.Tensor):
+        raise ValueError(f"{what}: tensor expected")
+    if v.dtype != dtype:
+        raise ValueError(f"{what}: {dtype} expected, got {v.dtype}")
+    if v.numel() != 3 * n_nodes:
+        raise ValueError(f"{what}: {3 * n_nodes} entries expected, got {v.numel()}")
+    if not v.is_cuda or v.device != torch.device(device):
+        raise ValueError(f"{what}: tensor on {device} expected, got {v.device}")
+    if not v.is_contiguous():
+        raise ValueError(f"{what}: contiguous tensor expected")
+    return v
 
 
 def _stream():
@@ -255,13 +274,23 @@ class Operator:
     def _vec(self, dtype=torch.float64):
         return torch.empty(self.n_nodes, 3, dtype=dtype, device=self.device)
 
-    def _in(self, v, dtype=torch.float64):
-        if v.dtype != dtype or v.numel() != self.n_dof or not v.is_cuda:
-            raise ValueError(f"expected {dtype} device vector with {self.n_dof} entries")
-        return v.contiguous()
+    def _in(self, v, dtype=torch.float64, what="vector"):
+        if isinstance(v, torch.Tensor) and v.dtype == dtype and v.numel() == self.n_dof:
+            v = v.contiguous()
+        return _vec(v, self.n_nodes, dtype, self.device, what)
+
+    def _out(self, out, dtype):
+        return self._vec(dtype) if out is None else _vec(out, self.n_nodes, dtype, self.device, "out")
+
+    def state_version(self) -> int:
+        """Counter of the stored linearisation this operator applies (bumped whenever
+        it is overwritten)."""
+        v = C.c_uint64()
+        _check(lib().hpmg_op_state_version(self.h, C.byref(v)))
+        return int(v.value)
 
     def qdata_setup(self, coords: torch.Tensor):
-        c = self._in(coords)
+        c = self._in(coords, what="coords")
         self._keep.append(c)
         _check(lib().hpmg_qdata_setup(self.h, _p(c), _stream()))
 
@@ -276,6 +305,9 @@ class Operator:
         local face 0..5)); constrained components 0."""
         import numpy as np
         nf = 0 if faces is None else len(faces)
+        if nf and (coords is None or traction is None):
+            raise ValueError("faces need coords and a traction")
+        coords = None if coords is None else self._in(coords, torch.float64, "coords")
         f = self._vec(torch.float64)
         fe = fi = ws = None
         nb = C.c_size_t(0)
@@ -288,7 +320,7 @@ class Operator:
         g = None if rho_g is None else (C.c_double * 3)(*[float(v) for v in rho_g])
         t = None if traction is None else (C.c_double * 3)(*[float(v) for v in traction])
         _check(lib().hpmg_external_load(self.h, None if g is None else C.cast(g, C.c_void_p),
-                                        None if coords is None else _p(coords.contiguous()), nf,
+                                        None if coords is None else _p(coords), nf,
                                         None if fe is None else _p(fe), None if fi is None else _p(fi),
                                         None if t is None else C.cast(t, C.c_void_p),
                                         None if ws is None else _p(ws), int(nb.value), _p(f), _stream()))
@@ -301,19 +333,20 @@ class Operator:
         nb = C.c_size_t()
         _check(lib().hpmg_state_initial_bytes(self.h, C.byref(nb)))
         self.sinit = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=self.device)
-        _check(lib().hpmg_state_initial(self.h, _p(self._in(u)), _p(self.sinit), int(nb.value), _stream()))
+        _check(lib().hpmg_state_initial(self.h, _p(self._in(u, what="u")), _p(self.sinit), int(nb.value),
+                                        _stream()))
 
     def residual(self, u, store_state: bool = True, out=None):
-        u = self._in(u)
-        r = self._vec() if out is None else out
+        u = self._in(u, what="u")
+        r = self._out(out, torch.float64)
         _check(lib().hpmg_residual(self.h, _p(u), _p(r), int(bool(store_state)), _stream()))
         return r
 
     def jacobian(self, du, precision="f64", mode="stored", u=None, out=None):
         prec, md = _prec(precision), _mode(mode)
-        du = self._in(du, _dtype(prec))
-        uu = None if u is None else self._in(u)
-        y = self._vec(_dtype(prec)) if out is None else out
+        du = self._in(du, _dtype(prec), "du")
+        uu = None if u is None else self._in(u, what="u")
+        y = self._out(out, _dtype(prec))
         _check(lib().hpmg_jacobian_apply(self.h, prec, md, _p(uu), _p(du), _p(y), _stream()))
         return y
 
@@ -330,15 +363,15 @@ class Operator:
         return d
 
     def energy(self, u) -> torch.Tensor:
-        u = self._in(u)
+        u = self._in(u, what="u")
         psi = torch.empty((), dtype=torch.float64, device=self.device)
         _check(lib().hpmg_energy(self.h, _p(u), _p(psi), _stream()))
         return psi
 
     def residual_vjp(self, u, w, mode="recompute", want_params=True, precision="f64"):
         prec = _prec(precision)
-        u = self._in(u)
-        w = self._in(w, _dtype(prec))
+        u = self._in(u, what="u")
+        w = self._in(w, _dtype(prec), "w")
         ub = self._vec(_dtype(prec))
         mub = lamb = None
         if want_params:
@@ -351,34 +384,54 @@ class Operator:
 
 def hpmg_prolong_add(coarse: Operator, fine: Operator, xc, yf, precision="f64"):
     prec = _prec(precision)
-    _check(lib().hpmg_prolong_add(coarse.h, fine.h, prec, _p(xc.contiguous()), _p(yf), _stream()))
+    xc = coarse._in(xc, _dtype(prec), "xc")
+    _vec(yf, fine.n_nodes, _dtype(prec), fine.device, "yf")
+    _check(lib().hpmg_prolong_add(coarse.h, fine.h, prec, _p(xc), _p(yf), _stream()))
     return yf
 
 
 def hpmg_restrict(fine: Operator, coarse: Operator, rf, precision="f64", out=None):
     prec = _prec(precision)
-    rc = coarse._vec(_dtype(prec)) if out is None else out
-    _check(lib().hpmg_restrict(fine.h, coarse.h, prec, _p(rf.contiguous()), _p(rc), _stream()))
+    rf = fine._in(rf, _dtype(prec), "rf")
+    rc = coarse._out(out, _dtype(prec))
+    _check(lib().hpmg_restrict(fine.h, coarse.h, prec, _p(rf), _p(rc), _stream()))
     return rc
 
 
+def _same_vectors(*vs):
+    v0 = vs[0]
+    for v in vs:
+        if not isinstance(v, torch.Tensor) or not v.is_cuda or not v.is_contiguous():
+            raise ValueError("contiguous device tensors expected")
+        if v.dtype != v0.dtype or v.numel() != v0.numel() or v.device != v0.device:
+            raise ValueError("vectors of one dtype, size and device expected")
+    if v0.dtype not in (torch.float64, torch.float32):
+        raise ValueError("float64 or float32 vectors expected")
+
+
 def hpmg_vec_dot(x, y, scratch=None):
+    _same_vectors(x, y)
     prec = _prec(x.dtype)
     if scratch is None:
         scratch = torch.empty(REDUCE_SCRATCH, dtype=torch.float64, device=x.device)
+    elif scratch.dtype != torch.float64 or scratch.numel() < REDUCE_SCRATCH or scratch.device != x.device:
+        raise ValueError(f"scratch must be float64 with at least {REDUCE_SCRATCH} entries on {x.device}")
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(lib().hpmg_vec_dot(prec, x.numel(), _p(x), _p(y), _p(out), _p(scratch), _stream()))
     return out
 
 
 def hpmg_vec_axpby(alpha, x, beta, y):
+    _same_vectors(x, y)
     _check(lib().hpmg_vec_axpby(_prec(x.dtype), x.numel(), float(alpha), _p(x), float(beta), _p(y), _stream()))
     return y
 
 
 def hpmg_vec_cast(x, dtype):
+    if not isinstance(x, torch.Tensor) or x.dtype not in (torch.float64, torch.float32) or not x.is_cuda:
+        raise ValueError("float64 or float32 device tensor expected")
     y = torch.empty(x.shape, dtype=dtype, device=x.device)
-    _check(lib().hpmg_vec_cast(x.numel(), _prec(dtype), _p(x), _p(y), _stream()))
+    _check(lib().hpmg_vec_cast(x.numel(), _prec(dtype), _p(x.contiguous()), _p(y), _stream()))
     return y
 
 
@@ -414,10 +467,16 @@ class PMG:
             _lib.hpmg_mg_destroy(h)
             self.h = None
 
+    def _fine_vec(self, v, what):
+        """FP64 vector of the fine level (the drivers' and the V-cycle's interface)."""
+        return self.levels[0]._in(v, torch.float64, what)
+
     def _seed_array(self, seeds):
-        seeds = [s.contiguous() for s in seeds]
+        seeds = list(seeds)
         if len(seeds) < len(self.levels) - 1:
             raise ValueError("one rough seed vector per smoothed level")
+        seeds = [self.levels[l]._in(s, torch.float64, f"seed {l}") if l < len(self.levels) - 1 else s
+                 for l, s in enumerate(seeds)]
         self._seeds = seeds
         arr = (C.c_void_p * len(seeds))(*[s.data_ptr() for s in seeds])
         self._seed_c = arr
@@ -427,8 +486,9 @@ class PMG:
         _check(lib().hpmg_mg_setup(self.h, self._seed_array(seeds), _stream()))
 
     def vcycle(self, r):
+        r = self._fine_vec(r, "r")
         z = torch.empty_like(r)
-        _check(lib().hpmg_mg_vcycle(self.h, _p(r.contiguous()), _p(z), _stream()))
+        _check(lib().hpmg_mg_vcycle(self.h, _p(r), _p(z), _stream()))
         return z
 
     def info(self, level):
@@ -444,22 +504,31 @@ class PMG:
                 "applies_per_level": v[3:3 + len(self.levels)]}
 
     def fcg(self, b, x=None, rtol=1e-8, maxit=500):
-        x = torch.zeros_like(b) if x is None else x
+        b = self._fine_vec(b, "b")
+        x = torch.zeros_like(b) if x is None else _vec(x, self.levels[0].n_nodes, torch.float64,
+                                                        self.levels[0].device, "x")
         its, rel = C.c_int(), C.c_double()
-        _check(lib().hpmg_fcg_solve(self.levels[0].h, self.h, _p(b.contiguous()), _p(x), float(rtol),
+        _check(lib().hpmg_fcg_solve(self.levels[0].h, self.h, _p(b), _p(x), float(rtol),
                                     int(maxit), C.byref(its), C.byref(rel), _stream()))
         return x, int(its.value), float(rel.value)
 
     def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
-               line_search=True, monitor=False, f_ext=None):
+               line_search=True, monitor=False, f_ext=None, max_total_newton=None, max_total_krylov=None):
+        _vec(u, self.levels[0].n_nodes, torch.float64, self.levels[0].device, "u")
+        lift = self._fine_vec(lift, "lift")
+        f_ext = None if f_ext is None else self._fine_vec(f_ext, "f_ext")
         prm = NewtonParams()
         lib().hpmg_newton_default_params(C.byref(prm))
         prm.rtol, prm.max_newton, prm.lin_rtol = rtol, max_newton, lin_rtol
         prm.lin_maxit, prm.line_search = lin_maxit, int(bool(line_search))
         prm.monitor = int(bool(monitor))
+        if max_total_newton is not None:
+            prm.max_total_newton = int(max_total_newton)
+        if max_total_krylov is not None:
+            prm.max_total_krylov = int(max_total_krylov)
         stats = (C.c_double * (4 + n_steps))()
-        st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()),
-                                     None if f_ext is None else _p(f_ext.contiguous()), int(n_steps),
+        st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift),
+                                     None if f_ext is None else _p(f_ext), int(n_steps),
                                      C.byref(prm), self._seed_array(seeds), C.cast(stats, C.c_void_p),
                                      _stream())
         s = list(stats)
@@ -475,13 +544,15 @@ class PMG:
     def set_state(self, u):
         """Stores the linearisations of rediscretised coarse levels at the injection of
         ``u`` (no-op for Galerkin levels)."""
-        _check(lib().hpmg_mg_set_state(self.h, _p(u.contiguous()), _stream()))
+        _check(lib().hpmg_mg_set_state(self.h, _p(self._fine_vec(u, "u")), _stream()))
 
     def lbfgs(self, u, lift, n_steps, seeds, rtol=1e-8, max_its=200, memory=5, line_search=True,
               monitor=False, f_ext=None):
         """L-BFGS load stepping with this V-cycle as the initial inverse Hessian; ``u``
         (FP64 [N][3]) is updated in place.  Returns ``u`` and a statistics dict."""
-        import torch
+        _vec(u, self.levels[0].n_nodes, torch.float64, self.levels[0].device, "u")
+        lift = self._fine_vec(lift, "lift")
+        f_ext = None if f_ext is None else self._fine_vec(f_ext, "f_ext")
         prm = LbfgsParams()
         lib().hpmg_lbfgs_default_params(C.byref(prm))
         prm.rtol, prm.max_its, prm.memory = rtol, max_its, memory
@@ -490,8 +561,8 @@ class PMG:
         _check(lib().hpmg_lbfgs_workspace_bytes(self.h, int(memory), C.byref(nb)))
         ws = torch.empty(max(int(nb.value), 256), dtype=torch.uint8, device=u.device)
         stats = (C.c_double * (4 + n_steps))()
-        st = lib().hpmg_lbfgs_solve(self.levels[0].h, self.h, _p(u), _p(lift.contiguous()),
-                                    None if f_ext is None else _p(f_ext.contiguous()), int(n_steps),
+        st = lib().hpmg_lbfgs_solve(self.levels[0].h, self.h, _p(u), _p(lift),
+                                    None if f_ext is None else _p(f_ext), int(n_steps),
                                     C.byref(prm), self._seed_array(seeds), _p(ws), int(nb.value),
                                     C.cast(stats, C.c_void_p), _stream())
         s = list(stats)

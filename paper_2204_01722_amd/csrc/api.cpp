@@ -268,6 +268,13 @@ int hpmg_op_info(hpmg_op op, int64_t *info) {
   return HPMG_OK;
 }
 
+int hpmg_op_state_version(hpmg_op op, uint64_t *version) {
+  if (!op || !version) return fail(HPMG_ERR_ARG, "op_state_version: null argument");
+  const hpmg_op_s *f = op->fine ? op->fine : op;
+  *version = f->state_version;
+  return HPMG_OK;
+}
+
 int hpmg_op_query_flags(hpmg_op op, void *stream, unsigned *flags) {
   int st = check_ready(op, "query_flags");
   if (st) return st;
