@@ -665,7 +665,15 @@ void hpmg_newton_default_params(hpmg_newton_params *p) {
   p->lin_maxit = 500;
   p->line_search = 1;
   p->monitor = 0;
+  p->max_total_newton = 200;
+  p->max_total_krylov = 20000;
 }
+
+// Iteration budget of a whole Newton solve (every load step and retry together).
+struct NewtonBudget {
+  int newton_left, krylov_left;
+  bool exhausted = false;
+};
 
 // Stores the linearisation at u (residual with state) and returns ||F(u)||.
 static int store_state(hpmg_op fine, hpmg_mg_s *mg, const double *u, hipStream_t s, double *fnorm) {
@@ -690,7 +698,7 @@ static int store_state(hpmg_op fine, hpmg_mg_s *mg, const double *u, hipStream_t
 // error that tells the caller to cut the increment.
 static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *f_ext,
                           const hpmg_newton_params *prm, const double *const *seeds, void *stream, double load,
-                          int *its_out, int *lin_out, double *rel_out) {
+                          NewtonBudget *budget, int *its_out, int *lin_out, double *rel_out) {
   int st;
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
@@ -710,6 +718,11 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *
   int its = 0;
   while (f0 > 0.0 && !(fn <= prm->rtol * f0)) {
     if (its >= prm->max_newton) return fail(HPMG_ERR_NOT_CONVERGED, "newton: iteration limit");
+    if (budget->newton_left <= 0 || budget->krylov_left <= 0) {
+      budget->exhausted = true;
+      return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: total iteration budget spent");
+    }
+    budget->newton_left--;
     // the fine state belongs to the previous converged point in the predictor
     // iteration (saved in nu0), to u afterwards
     if (has_redisc(mg) && (st = set_state(mg, its == 0 ? mg->nu0 : u, s))) return st;
@@ -718,8 +731,9 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *
     HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
     int lits = 0;
     double lrel = 0.0;
-    st = do_fcg(fine, mg, ut, du, prm->lin_rtol, prm->lin_maxit, &lits, &lrel, s);
+    st = do_fcg(fine, mg, ut, du, prm->lin_rtol, std::min(prm->lin_maxit, budget->krylov_left), &lits, &lrel, s);
     *lin_out += lits;
+    budget->krylov_left -= lits;
     if (st && st != HPMG_ERR_NOT_CONVERGED && st != HPMG_ERR_BREAKDOWN) return st;
     const int lin_st = st;
     double alpha = 1.0;
@@ -782,10 +796,13 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, c
   if (!u || !lift || !prm || !seeds || !stats) return fail(HPMG_ERR_ARG, "newton_solve: null argument");
   if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "newton_solve: 1 <= n_steps <= 60");
   if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "newton_solve: call qdata_setup first");
+  if (prm->max_total_newton < 1 || prm->max_total_krylov < 1)
+    return fail(HPMG_ERR_ARG, "newton_solve: the total iteration budgets must be positive");
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
   for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;
   int total_newton = 0, total_lin = 0, cuts = 0;
+  NewtonBudget budget{prm->max_total_newton, prm->max_total_krylov};
   double final_rel = 0.0;
   // Load increments of 1/n_steps; an increment whose Newton solve fails is retried from
   // the previous converged state in halves (at most 6 halvings in a row); after a
@@ -809,8 +826,8 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, c
       HPMG_HIP(launch_axpby(HPMG_F64, n, inc / n_steps, lift, 1.0, u, s));
       int its = 0;
       double rel = 0.0;
-      st = newton_at_load(fine, mg, u, f_ext, prm, seeds, stream, (step + done + inc) / n_steps, &its, &total_lin,
-                          &rel);
+      st = newton_at_load(fine, mg, u, f_ext, prm, seeds, stream, (step + done + inc) / n_steps, &budget, &its,
+                          &total_lin, &rel);
       if (st && prm->monitor)
         std::fprintf(stderr, "[newton] load %.6f failed (%s); halving the increment\n", (step + done + inc) / n_steps,
                      hpmg_last_error());
@@ -828,11 +845,18 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, c
           st != HPMG_ERR_BREAKDOWN)
         return st;
       ++cuts;
-      if (++halvings > 6) {
+      if (budget.exhausted || ++halvings > 6) {
         stats[0] = total_newton;
         stats[1] = total_lin;
         stats[2] = final_rel;
         stats[3] = cuts;
+        if (budget.exhausted) {
+          // u goes back to the last converged load level
+          HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, u, s));
+          return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: total iteration budget spent (" +
+                                                  std::to_string(total_newton) + " Newton, " +
+                                                  std::to_string(total_lin) + " FCG iterations)");
+        }
         return fail(HPMG_ERR_NOT_CONVERGED, "newton_solve: load increment failed after 6 halvings in a row");
       }
       HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, u, s));

@@ -330,6 +330,33 @@ def test_newton_cuts_the_load_increment():
     assert rel(t2n(u), ref) < 1e-7
 
 
+@pytest.mark.parametrize("budget", [{"max_total_newton": 6}, {"max_total_krylov": 3}])
+def test_newton_stops_when_the_total_budget_is_spent(budget):
+    """The load-cut problem above with a total iteration budget too small for it: the
+    solve stops with HPMG_ERR_NOT_CONVERGED within the budget (instead of retrying
+    halvings without end) and leaves u at the last converged load level, an
+    equilibrium with no inverted element."""
+    import torch
+    from paper_2204_01722_amd.binding import PMG, HpmgError
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("newton_budget", **budget)
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(3, 2, jitter=0.1)
+    H = Hierarchy(m, [2, 1], faces=faces)
+    lift = _dev(inputs.affine_lifting(m, (-0.5, 0.0, 0.0)))
+    pmg = PMG(H.ops, precision="f64")
+    u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    with pytest.raises(HpmgError) as err:
+        pmg.newton(u, lift, 1, H.seeds(7), rtol=1e-10, max_newton=4, lin_rtol=1e-8, **budget)
+    print(f"[newton_budget] {err.value}", flush=True)
+    assert err.value.status == 9  # HPMG_ERR_NOT_CONVERGED
+    assert "budget" in str(err.value)
+    r = H.fine.residual(u, store_state=True)
+    assert H.fine.query_flags() == 0
+    scale = torch.linalg.norm(H.fine.jacobian(lift))
+    assert float(torch.linalg.norm(r)) <= 1e-8 * float(scale)
+
+
 def test_lbfgs_matches_oracle():
     """L-BFGS with the V-cycle as initial inverse Hessian (Q4 -> Q2 -> Q1, 2^3 elements,
     x = 0 clamped, x = 1 face pulled by 0.2 in two load steps): the GPU driver takes the
