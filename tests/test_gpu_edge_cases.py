@@ -1,0 +1,184 @@
+"""GPU parity on the degenerate and extreme cases of the constitutive map (Section II-A):
+the reference configuration, strains small enough that det F - 1 formed naively would
+cancel, rigid rotations, and a field close to element inversion.
+
+Each case reports the relative error in the 2-norm and in the max-norm; the assertions
+are on the 2-norm (1e-12 FP64, 1e-5 FP32) unless stated."""
+import numpy as np
+import pytest
+
+from _support import LAM, MU, ensure_built, gpu_available, print_case, rel, t2n
+from oracle import fem
+from paper_2204_01722_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-12, 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    if not gpu_available():
+        pytest.skip("no GPU")
+    ensure_built()
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _errs(name, got, ref):
+    """Relative errors (2-norm, max-norm) of ``got`` against ``ref``, printed."""
+    got = np.asarray(got, np.float64).reshape(-1)
+    ref = np.asarray(ref, np.float64).reshape(-1)
+    e2 = rel(got, ref)
+    mx = np.abs(ref).max()
+    einf = np.abs(got - ref).max() / (mx if mx > 0 else 1.0)
+    print(f"  {name}: rel 2-norm {e2:.2e}, rel max-norm {einf:.2e}", flush=True)
+    return e2, einf
+
+
+def _hier(n, p, faces=None):
+    from paper_2204_01722_amd.problem import Hierarchy
+    m = inputs.box_mesh(n, p, jitter=0.05)
+    return m, Hierarchy(m, [p], faces=faces)
+
+
+def _rotation(a, b, c):
+    def rx(t):
+        return np.array([[1, 0, 0], [0, np.cos(t), -np.sin(t)], [0, np.sin(t), np.cos(t)]])
+
+    def ry(t):
+        return np.array([[np.cos(t), 0, np.sin(t)], [0, 1, 0], [-np.sin(t), 0, np.cos(t)]])
+
+    def rz(t):
+        return np.array([[np.cos(t), -np.sin(t), 0], [np.sin(t), np.cos(t), 0], [0, 0, 1]])
+    return rz(c) @ ry(b) @ rx(a)
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_reference_configuration(p):
+    """u = 0: the residual is exactly zero (J - 1 = 0, log J = 0, tau = 0 with no
+    rounding), and the Jacobian is the linear-elastic stiffness (the oracle's tangent
+    at u = 0, pinned to the Voigt assembly)."""
+    print_case("reference_configuration", p=p)
+    m, H = _hier(3, p)
+    op = H.fine
+    u = np.zeros((m.n_nodes, 3))
+    r = t2n(op.residual(_dev(u), store_state=True))
+    assert np.all(r == 0.0)
+    du = inputs.random_vector(m.n_nodes, 2)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM)
+    e2, _ = _errs("J(0) du", t2n(op.jacobian(_dev(du), "f64")), y_ref)
+    assert e2 < TOL64
+    op.state_cast_f32()
+    e2, _ = _errs("J(0) du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
+    assert e2 < TOL32
+    # rigid translations are in the null space
+    t = np.tile([1.0, -2.0, 0.5], (m.n_nodes, 1))
+    yt = t2n(op.jacobian(_dev(t), "f64"))
+    assert np.abs(yt).max() <= 1e-13 * np.abs(y_ref).max()
+    assert op.query_flags() == 0
+
+
+@pytest.mark.parametrize("amplitude", [1e-6, 1e-9])
+@pytest.mark.parametrize("p", [2, 4])
+def test_small_strain(amplitude, p):
+    """At |H| ~ 1e-6 .. 1e-9 the residual is linear in u to rounding; J - 1 and log J
+    must keep full relative accuracy (cancellation-free forms) for the GPU to match the
+    oracle to 1e-12 relative, stored and recomputed."""
+    print_case("small_strain", amplitude=amplitude, p=p)
+    faces = {"x0": (1, 1, 1)}
+    m, H = _hier(3, p, faces)
+    op = H.fine
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    mask = inputs.face_mask(m, faces)
+    u = amplitude * inputs.sinusoid(m.coords, m.L) + inputs.random_vector(m.n_nodes, 1) * amplitude * 1e-2
+    u[mask.astype(bool)] = 0.0
+    du = inputs.random_vector(m.n_nodes, 2)
+    r_ref = fem.residual(d, u, MU, LAM, mask)
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
+    r = t2n(op.residual(_dev(u), store_state=True))
+    e2, _ = _errs("residual", r, r_ref)
+    assert e2 < TOL64
+    e2, _ = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64", "stored")), y_ref)
+    assert e2 < TOL64
+    e2, _ = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=_dev(u))), y_ref)
+    assert e2 < TOL64
+    # the residual is the linear-elastic one to O(|u|^2)
+    y_lin = fem.jacobian_apply(d, np.zeros_like(u), u, MU, LAM, mask)
+    assert rel(r, y_lin) < 50 * amplitude
+    assert op.query_flags() == 0
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_rigid_rotation(p):
+    """u = (R - I) X: F = R, J = 1, tau = 0, so the residual vanishes up to rounding, and
+    the tangent is the linear-elastic stiffness rotated node by node,
+    J(u) w = R K_lin (R^T w)."""
+    print_case("rigid_rotation", p=p)
+    m, H = _hier(3, p)
+    op = H.fine
+    R = _rotation(0.9, -1.2, 2.1)
+    u = m.coords @ R.T - m.coords
+    r = t2n(op.residual(_dev(u), store_state=True))
+    print(f"  |r|_inf = {np.abs(r).max():.2e}", flush=True)
+    assert np.abs(r).max() <= 1e-13
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    w = inputs.random_vector(m.n_nodes, 4)
+    y_ref = fem.jacobian_apply(d, np.zeros_like(u), w @ R, MU, LAM) @ R.T
+    e2, _ = _errs("J(R) w stored", t2n(op.jacobian(_dev(w), "f64")), y_ref)
+    assert e2 < TOL64
+    e2, _ = _errs("J(R) w recompute", t2n(op.jacobian(_dev(w), "f64", "recompute", u=_dev(u))), y_ref)
+    assert e2 < TOL64
+    # the oracle's own tangent at the rotated state agrees with the rotated stiffness
+    assert rel(fem.jacobian_apply(d, u, w, MU, LAM), y_ref) < 1e-12
+    assert op.query_flags() == 0
+
+
+def _min_j(d, u):
+    _, _, gp = fem.geometry(d)
+    H = np.einsum("eai,eqJa->eqiJ", u[d.elem_nodes], gp)
+    return float((1.0 + fem.j_minus_1(H)).min())
+
+
+def test_near_inversion():
+    """A smooth field scaled until the smallest J over the quadrature points is 0.05
+    (close to inverting an element): residual and Jacobian still match the oracle to
+    1e-12 in FP64, and the FP32 apply to 1e-5."""
+    print_case("near_inversion")
+    faces = {"x0": (1, 1, 1)}
+    m, H = _hier(3, 2, faces)
+    op = H.fine
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    mask = inputs.face_mask(m, faces)
+    s = inputs.sinusoid(m.coords, m.L)
+    lo, hi = 0.0, 0.05
+    while _min_j(d, hi * s) > 0.05:
+        lo, hi = hi, hi + 0.05
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if _min_j(d, mid * s) > 0.05:
+            lo = mid
+        else:
+            hi = mid
+    u = lo * s
+    jmin = _min_j(d, u)
+    print(f"  amplitude {lo:.6f}, min J {jmin:.4f}", flush=True)
+    assert 0.049 < jmin < 0.06
+    du = inputs.random_vector(m.n_nodes, 2)
+    r_ref = fem.residual(d, u, MU, LAM, mask)
+    y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
+    ut = _dev(u)
+    e2, _ = _errs("residual", t2n(op.residual(ut, store_state=True)), r_ref)
+    assert e2 < TOL64
+    e2, _ = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64")), y_ref)
+    assert e2 < TOL64
+    e2, _ = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=ut)), y_ref)
+    assert e2 < TOL64
+    op.state_cast_f32()
+    e2, _ = _errs("J du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
+    assert e2 < TOL32
+    assert op.query_flags() == 0
