@@ -224,12 +224,25 @@ int hpmg_residual_vjp(hpmg_op op, int precision, int mode, const double *u, cons
 
 /* ---------------------------------------------------------------------------------
  * Vector kernels used by the solvers (deterministic FP64 reductions).
- * n counts scalars.  Reductions write a device double and do not synchronise.
+ * n counts scalars (x and y may be NULL when n = 0).  Reductions write a device double
+ * and do not synchronise.
  * --------------------------------------------------------------------------------- */
 /* scratch: device double buffer of at least HPMG_REDUCE_SCRATCH entries. */
 #define HPMG_REDUCE_SCRATCH 2048
 int hpmg_vec_dot(int precision, int64_t n, const void *x, const void *y, double *out,
                  double *scratch, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hpmg_vec_dot without the scratch
+ * argument.  Its partial sums live in a library-owned static device array of
+ * HPMG_NOALLOC_SCRATCH_DOUBLES doubles (4 KiB) that each GPU holds until the process
+ * ends; it allocates nothing and makes no allocating call.  The reduction's grid is
+ * fixed, so any n >= 0 fits (no size is too large).  Same kernels, same summation order:
+ * the result equals hpmg_vec_dot's bit for bit.  The current device must be the one
+ * `stream` belongs to.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (different streams or threads without ordering) race and give wrong sums. */
+#define HPMG_NOALLOC_SCRATCH_DOUBLES 512
+int hpmg_vec_dot_noalloc(int precision, int64_t n, const void *x, const void *y, double *out,
+                         void *stream);
 int hpmg_vec_axpby(int precision, int64_t n, double alpha, const void *x, double beta, void *y,
                    void *stream); /* y = alpha x + beta y */
 int hpmg_vec_cast(int64_t n, int to_precision, const void *x, void *y, void *stream);

@@ -78,6 +78,7 @@ _SIGS = {
     "hpmg_energy": ([_VP, _VP, _VP, _VP], _I),
     "hpmg_residual_vjp": ([_VP, _I, _I, _VP, _VP, _VP, _VP, _VP, _VP], _I),
     "hpmg_vec_dot": ([_I, _I64, _VP, _VP, _VP, _VP, _VP], _I),
+    "hpmg_vec_dot_noalloc": ([_I, _I64, _VP, _VP, _VP, _VP], _I),
     "hpmg_vec_axpby": ([_I, _I64, _D, _VP, _D, _VP, _VP], _I),
     "hpmg_vec_cast": ([_I64, _I, _VP, _VP, _VP], _I),
     "hpmg_mg_default_params": ([C.POINTER(MGParams)], None),
@@ -418,6 +419,18 @@ def hpmg_vec_dot(x, y, scratch=None):
         raise ValueError(f"scratch must be float64 with at least {REDUCE_SCRATCH} entries on {x.device}")
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(lib().hpmg_vec_dot(prec, x.numel(), _p(x), _p(y), _p(out), _p(scratch), _stream()))
+    return out
+
+
+def hpmg_vec_dot_noalloc(x, y, out=None):
+    """``x . y`` into a device FP64 scalar without a scratch buffer (the library keeps
+    the partial sums in a static device array; calls overlapping on one GPU race)."""
+    _same_vectors(x, y)
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=x.device)
+    elif out.dtype != torch.float64 or out.numel() < 1 or out.device != x.device:
+        raise ValueError(f"out must be a float64 tensor on {x.device}")
+    _check(lib().hpmg_vec_dot_noalloc(_prec(x.dtype), x.numel(), _p(x), _p(y), _p(out), _stream()))
     return out
 
 

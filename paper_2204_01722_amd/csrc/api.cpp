@@ -2,6 +2,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -542,8 +543,54 @@ int hpmg_vec_dot(int precision, int64_t n, const void *x, const void *y, double 
                  void *stream) {
   int st = check_prec(precision, "vec_dot");
   if (st) return st;
-  if (!x || !y || !out || !scratch || n < 0) return fail(HPMG_ERR_ARG, "vec_dot: bad argument");
+  if ((n > 0 && (!x || !y)) || !out || !scratch || n < 0) return fail(HPMG_ERR_ARG, "vec_dot: bad argument");
   HPMG_HIP(launch_dot(precision, n, x, y, scratch, out, S(stream)));
+  return HPMG_OK;
+}
+
+}  // extern "C"
+
+// Partial sums of hpmg_vec_dot_noalloc: one per workgroup of the reduction's fixed
+// grid, every one overwritten by every call (nothing needs clearing).  Each GPU holds
+// its own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not the device array: kernels get the address from scratch_address().
+static __device__ __align__(256) double scratch[HPMG_NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+int scratch_address(void **out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "vec_dot_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(HPMG_ERR_UNSUPPORTED, "vec_dot_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "vec_dot_noalloc: hipGetSymbolAddress(scratch)");
+    if (!p) return fail(HPMG_ERR_HIP, "vec_dot_noalloc: null address of the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return HPMG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int hpmg_vec_dot_noalloc(int precision, int64_t n, const void *x, const void *y, double *out, void *stream) {
+  int st = check_prec(precision, "vec_dot_noalloc");
+  if (st) return st;
+  if ((n > 0 && (!x || !y)) || !out || n < 0) return fail(HPMG_ERR_ARG, "vec_dot_noalloc: bad argument");
+  // The reduction's grid is fixed, so the scratch need does not grow with n.
+  static_assert(RED_BLOCKS <= HPMG_NOALLOC_SCRATCH_DOUBLES, "scratch smaller than the reduction grid");
+  void *partial = nullptr;
+  if ((st = scratch_address(&partial))) return st;
+  HPMG_HIP(launch_dot(precision, n, x, y, static_cast<double *>(partial), out, S(stream)));
   return HPMG_OK;
 }
 
