@@ -355,7 +355,6 @@ int hpmg_jacobian_apply(hpmg_op op, int precision, int mode, const double *u, co
     if (op->fine) return fail(HPMG_ERR_ARG, "jacobian_apply: initial-configuration modes need a fine operator");
     if (precision != HPMG_F64) return fail(HPMG_ERR_UNSUPPORTED, "jacobian_apply: initial-configuration modes are FP64");
     if (!op->sinit_ready) return fail(HPMG_ERR_ARG, "jacobian_apply: call hpmg_state_initial first");
-    if (use_atomic_scatter()) return fail(HPMG_ERR_UNSUPPORTED, "jacobian_apply: initial-configuration modes need the record scatter");
   } else {
     return fail(HPMG_ERR_ARG, "jacobian_apply: bad mode");
   }

@@ -174,7 +174,6 @@ hipError_t launch_vjp(const hpmg_op_s &op, int prec, int mode, const double *u, 
                       double *mub, double *lamb, hipStream_t s);
 hipError_t launch_export_qdata(const hpmg_op_s &op, double *out, hipStream_t s);
 hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s);
-bool use_atomic_scatter();
 
 // Vector kernels.
 hipError_t launch_init_bc(int prec, int64_t n_nodes, const uint8_t *mask, const void *x, void *y,

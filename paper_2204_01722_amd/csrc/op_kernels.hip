@@ -7,7 +7,8 @@
 //   gather (E)  ->  sum-factorised interpolation, three 1D contractions staged in LDS
 //   ->  collocated derivative B_xi B_I^+ (three more contractions, Section II-B)
 //   ->  pointwise constitutive map in registers (Section II-A)
-//   ->  transposed derivative and interpolation in LDS  ->  atomic scatter-add (E^T).
+//   ->  transposed derivative and interpolation in LDS  ->  element records, summed per
+//       node in a fixed order by a node-centric assembly pass (E^T, no atomics).
 //
 // Quadrature-point data are read/written as [tile][field][ET*Q^3] so each field of a
 // tile is one contiguous, coalesced sweep.  Dirichlet flags ride in the top bits of the
@@ -29,9 +30,6 @@ struct QT {
   static constexpr int NQ = ET * Q3;
   static constexpr int NT = tile_threads(Q);
 };
-
-__device__ __forceinline__ void atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 
 // One 1D contraction along direction DIR of an array with dims (N1, N2, N3), N1
 // fastest, for NC components stored back to back.  Output dims replace N_DIR by NO.
@@ -378,6 +376,15 @@ __device__ __forceinline__ int64_t xcd_tile() {
   return (int64_t)x * m + (x < r ? x : r) + j;
 }
 
+// Record traffic of FP64 order-4 operators (P = 5) goes through contiguous nontemporal
+// sweeps: the Jacobian kernel's records and the assembly's output (measured: 197 against
+// 217 us per Q4 apply on 34^3 elements); at the other orders and in FP32 the per-node
+// stores were as fast or faster.
+template <typename T>
+__host__ __device__ constexpr bool sweep_records(int P) {
+  return std::is_same<T, double>::value && P == 5;
+}
+
 __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
   return mu_e ? mu_e[e] : mu0;
 }
@@ -408,18 +415,6 @@ __device__ __forceinline__ void store_record(T *__restrict__ ev, int64_t e, cons
   p[0] = x0;
   p[1] = x1;
   p[2] = x2;
-}
-
-// Adds the three components of a node from LDS [c][P^3] into v (skipping constrained
-// components when `masked`).
-template <typename T>
-__device__ __forceinline__ void scatter_node(T *__restrict__ v, uint32_t w, bool masked, const T *a, int q,
-                                             int P3) {
-  const T x0 = a[q], x1 = a[P3 + q], x2 = a[2 * P3 + q];
-  T *p = v + (int64_t)(w & EMAP_ID_MASK) * 3;
-  if (!(masked && ((w >> EMAP_BC_SHIFT) & 1u))) atomic_add(p, x0);
-  if (!(masked && ((w >> (EMAP_BC_SHIFT + 1)) & 1u))) atomic_add(p + 1, x1);
-  if (!(masked && ((w >> (EMAP_BC_SHIFT + 2)) & 1u))) atomic_add(p + 2, x2);
 }
 
 // ------------------------------------------------------------------------------------
@@ -474,8 +469,8 @@ template <int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
     const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ geo,
     const double *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, double *__restrict__ r, double *__restrict__ state,
-    unsigned *__restrict__ flags, double *__restrict__ ev, int64_t E) {
+    const double *__restrict__ lam_e, double *__restrict__ state, unsigned *__restrict__ flags,
+    double *__restrict__ ev, int64_t E) {
   using T = double;
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
@@ -533,84 +528,15 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    if (ev)
-      store_record(ev, e, a, q, P3);
-    else
-      scatter_node(r, w, true, a, q, P3);
-  }
+  if (live && q < P3) store_record(ev, e, a, q, P3);
 }
 
 // ------------------------------------------------------------------------------------
-// a5: Jacobian action from the stored linearisation (FP64 or FP32).
-// ------------------------------------------------------------------------------------
-template <typename T, int P, int Q>
-__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_stored(
-    const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
-    const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, T *__restrict__ y, T *__restrict__ ev, int64_t E) {
-  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
-  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
-  __shared__ T sB[Q * P], sD[Q * Q];
-  __shared__ T lds[ET * (S0 + S1)];
-  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t tile = xcd_tile();
-  const int64_t e = tile * ET + el;
-  const bool live = tq < NQ && e < E;
-  // Issue order matters (the vector-memory counter retires loads in order): tables and
-  // the element map first, then the gathered nodal values, then the linearisation,
-  // which stays in flight while the interpolation stages run in LDS.
-  uint32_t w = 0;
-  if (live && q < P3) w = emap[e * P3 + q];
-  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
-  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
-  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  T sv[NSTATE];
-  if (live && q < P3) gather_node(du, w, true, a, q, P3);
-  if (live) {
-    const T *s = state + tile * NSTATE * NQ + tq;
-#pragma unroll
-    for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
-  }
-  __syncthreads();
-  interp<T, P, Q, 3>(a, b, sB, q, live);
-  if (live) {
-    T G[3][3], A[3][3], tau[6];
-    grad_q<T, Q, 3>(b, sD, q, G);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
-#pragma unroll
-    for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
-    const T c = sv[15], W = sv[16];
-    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
-    T f[3][3];
-    jacobian_qf(G, A, tau, c, W, mu, lam, f);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) a[(i * 3 + k) * Q3 + q] = f[i][k];
-  }
-  __syncthreads();
-  grad_t_q<T, Q>(a, sD, q, b, live);
-  __syncthreads();
-  interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    if (ev)
-      store_record(ev, e, a, q, P3);
-    else
-      scatter_node(y, w, true, a, q, P3);
-  }
-}
-
-
-// ------------------------------------------------------------------------------------
-// a5: the same Jacobian action with register-blocked 1D contractions.
+// a5: Jacobian action from the stored linearisation (FP64 or FP32), with
+// register-blocked 1D contractions.
 //
-// In the kernel above every thread owns one point and each 1D contraction costs it one
-// LDS read per input of every output.  Here every contraction stage is run by "line
-// tasks": a task owns one line of points along the contraction direction (for one
+// With one thread per point, each 1D contraction would cost a thread one LDS read per
+// input of every output.  Here every contraction stage is run by "line tasks": a task owns one line of points along the contraction direction (for one
 // component), reads the line once, forms all of its outputs in registers from the 1D
 // table (the same for every lane, so it is read through the scalar cache, not LDS) and
 // writes them back in place.  That is one LDS read and one write per point and stage.
@@ -668,7 +594,9 @@ __device__ __forceinline__ void line_stage(T *buf, const T *__restrict__ M, int 
 // + grad_X u [+ C^-1, lambda log J]); T = double.
 // MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
 // lambda log J are rebuilt from grad_X u and J; T = double.
-template <typename T, int P, int Q, int MODE>
+// SWEEP: the tile's element records leave LDS in contiguous nontemporal sweeps (each
+// store instruction covers whole cache lines) instead of three strided stores per node.
+template <typename T, int P, int Q, int MODE, bool SWEEP>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const double *__restrict__ geo, const double *__restrict__ sinit,
@@ -874,7 +802,16 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   __syncthreads();
   line_stage<T, Q, 0, Q, P, true, P, P, ET, ELS>(lds, tB, tq, NT, nel);
   __syncthreads();
-  if (live && q < P3) {
+  if constexpr (SWEEP) {
+    // records [e][a][c] of the tile's elements are one contiguous run of nel P^3 3 values
+    T *o = ev + tile * (int64_t)(ET * P3 * 3);
+    const int nd = nel * P3 * 3;
+    for (int d = tq; d < nd; d += NT) {
+      const int r = d / 3, c = d - 3 * r, te = r / P3, a = r - te * P3;
+      const int an = (a % P) + Q * ((a / P) % P) + Q2 * (a / (P * P));
+      __builtin_nontemporal_store(lds[te * ELS + c * Q3 + an], o + d);
+    }
+  } else if (live && q < P3) {
     T *o = ev + ((int64_t)e * P3 + q) * 3;
     const T y0 = v[qn], y1 = v[Q3 + qn], y2 = v[2 * Q3 + qn];
     o[0] = y0;
@@ -1044,8 +981,7 @@ template <typename T, int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
     const uint32_t *__restrict__ emap, const double *__restrict__ u, const T *__restrict__ du,
     const double *__restrict__ geo, const T *__restrict__ tab, double mu0, double lam0,
-    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ y, T *__restrict__ ev,
-    int64_t E) {
+    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
   constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
   constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
   __shared__ T sB[Q * P], sD[Q * Q];
@@ -1100,12 +1036,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
   grad_t_q<T, Q>(a, sD, q, b, live);
   __syncthreads();
   interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) {
-    if (ev)
-      store_record(ev, e, a, q, P3);
-    else
-      scatter_node(y, w, true, a, q, P3);
-  }
+  if (live && q < P3) store_record(ev, e, a, q, P3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1695,6 +1626,41 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, const int32_t *__re
   }
 }
 
+// The same node sums with the output staged in LDS and written by the workgroup in
+// contiguous nontemporal sweeps (256 consecutive nodes = 768 consecutive values), so
+// every store instruction covers whole cache lines.
+template <typename T>
+__global__ __launch_bounds__(256) void k_assemble_staged(int64_t N, const int32_t *__restrict__ off,
+                                                         const int32_t *__restrict__ inc, const T *__restrict__ ev,
+                                                         const uint8_t *__restrict__ mask, const T *__restrict__ src,
+                                                         T fill, T *__restrict__ y) {
+  __shared__ T buf[3 * 256];
+  const int64_t n0 = (int64_t)blockIdx.x * 256, n = n0 + threadIdx.x;
+  if (n < N) {
+    const int32_t k0 = off[n], k1 = off[n + 1];
+    T a0 = 0, a1 = 0, a2 = 0;
+    for (int32_t k = k0; k < k1; ++k) {
+      const T *p = ev + (int64_t)inc[k] * 3;
+      a0 += p[0];
+      a1 += p[1];
+      a2 += p[2];
+    }
+    if (mask) {
+      const uint8_t *m = mask + n * 3;
+      if (m[0]) a0 = src ? src[n * 3] : fill;
+      if (m[1]) a1 = src ? src[n * 3 + 1] : fill;
+      if (m[2]) a2 = src ? src[n * 3 + 2] : fill;
+    }
+    buf[3 * threadIdx.x] = a0;
+    buf[3 * threadIdx.x + 1] = a1;
+    buf[3 * threadIdx.x + 2] = a2;
+  }
+  __syncthreads();
+  const int nv = 3 * (int)((N - n0) < 256 ? (N - n0) : 256);
+  T *o = y + n0 * 3;
+  for (int d = threadIdx.x; d < nv; d += 256) __builtin_nontemporal_store(buf[d], o + d);
+}
+
 // The same assembly fused with the partial dot product p . y of the assembled result
 // and the direction p (= src), one partial per workgroup (fixed tree): the Jacobi-PCG
 // step needs p^T A p right after A p.
@@ -1741,8 +1707,12 @@ template <typename T>
 hipError_t assemble(const hpmg_op_s &op, const T *src, T *y, hipStream_t s, T fill = T(0)) {
   int64_t g = (op.N + 255) / 256;
   if (g < 1) g = 1;
-  k_assemble<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src, fill,
-                                             y);
+  if (sweep_records<T>(op.P))
+    k_assemble_staged<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src,
+                                                      fill, y);
+  else
+    k_assemble<T><<<(unsigned)g, 256, 0, s>>>(op.N, op.csr_off, op.csr_inc, (const T *)op.evec, op.mask, src, fill,
+                                               y);
   return hipGetLastError();
 }
 
@@ -1801,40 +1771,15 @@ hipError_t launch_qdata(const hpmg_op_s &op, const double *X, hipStream_t s) {
 
 // Scatter flavour: HPMG_SCATTER=atomic selects hardware atomics into the output;
 // otherwise element records + the node-centric assembly pass (deterministic).
-bool use_atomic_scatter() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("HPMG_SCATTER");
-    v = (e && std::string(e) == "atomic") ? 1 : 0;
-  }
-  return v == 1;
-}
-
-// Stored-linearisation Jacobian: register-blocked line contractions unless
-// HPMG_ELEMENT_KERNEL=point selects the one-thread-per-point kernel.
-bool use_line_kernels() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("HPMG_ELEMENT_KERNEL");
-    v = (e && std::string(e) == "point") ? 0 : 1;
-  }
-  return v == 1;
-}
-
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
-  const bool atom = use_atomic_scatter();
-  if (atom) {
-    hipError_t e = launch_init_bc(HPMG_F64, op.N, op.mask, nullptr, r, s);
-    if (e != hipSuccess) return e;
-  }
-  double *ev = atom ? nullptr : op.evec;
 #define X(p, q)                                                                                  \
   if (op.P == p && op.Q == q) {                                                                  \
     k_residual<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, op.lam, \
-                                                              op.mu_e, op.lam_e, r,              \
-                                                              store ? op.state64 : nullptr, op.flags, ev, op.E); \
+                                                              op.mu_e, op.lam_e,                 \
+                                                              store ? op.state64 : nullptr, op.flags, op.evec, \
+                                                              op.E);                             \
     hipError_t e = hipGetLastError();                                                            \
-    if (e != hipSuccess || atom) return e;                                                       \
+    if (e != hipSuccess) return e;                                                               \
     return assemble<double>(op, nullptr, r, s);                                                  \
   }
   HPMG_PQ_LIST(X)
@@ -1844,36 +1789,30 @@ hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool
 
 template <typename T, int P, int Q>
 static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode, const double *u, const T *du,
-                              T *y, T *ev, const double *stop, hipStream_t s) {
+                              T *ev, const double *stop, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
+  constexpr bool SW = sweep_records<T>(P);
   if constexpr (std::is_same<T, double>::value) {
     if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
-      if (!ev) return hipErrorInvalidValue;  // these kernels only write element records
       if (mode == HPMG_INITIAL_NATIVE)
-        k_jacobian_lines<T, P, Q, 1><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+        k_jacobian_lines<T, P, Q, 1, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
             op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       else if (mode == HPMG_INITIAL_TUNED)
-        k_jacobian_lines<T, P, Q, 2><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+        k_jacobian_lines<T, P, Q, 2, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
             op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       else
-        k_jacobian_lines<T, P, Q, 3><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+        k_jacobian_lines<T, P, Q, 3, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
             op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
       return hipGetLastError();
     }
   }
-  if (mode == HPMG_STORED && ev && use_line_kernels()) {
-    k_jacobian_lines<T, P, Q, 0><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, nullptr, nullptr,
-                                                                           tab, f.mu, f.lam, f.mu_e, f.lam_e, ev,
-                                                                           op.E, stop);
-    return hipGetLastError();
-  }
   if (mode == HPMG_STORED) {
-    k_jacobian_stored<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, du, state, tab, f.mu, f.lam,
-                                                                        f.mu_e, f.lam_e, y, ev, op.E);
+    k_jacobian_lines<T, P, Q, 0, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
+        op.emap, du, state, nullptr, nullptr, tab, f.mu, f.lam, f.mu_e, f.lam_e, ev, op.E, stop);
   } else {
     k_jacobian_recompute<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, u, du, op.geo, tab, op.mu,
-                                                                           op.lam, op.mu_e, op.lam_e, y, ev, op.E);
+                                                                           op.lam, op.mu_e, op.lam_e, ev, op.E);
   }
   return hipGetLastError();
 }
@@ -1893,14 +1832,9 @@ template <typename T>
 static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, const T *du, T *y, hipStream_t s,
                              double *pq = nullptr, const double *stop = nullptr) {
   const hpmg_op_s &f = op.fine ? *op.fine : op;
-  const bool atom = use_atomic_scatter();
-  if (atom) {
-    hipError_t e = launch_init_bc(std::is_same<T, double>::value ? HPMG_F64 : HPMG_F32, op.N, op.mask, du, y, s);
-    if (e != hipSuccess) return e;
-  }
-  T *ev = atom ? nullptr : (T *)op.evec;
+  T *ev = (T *)op.evec;
   const int tprec = std::is_same<T, double>::value ? HPMG_F64 : HPMG_F32;
-  if (mode == HPMG_STORED && !atom && op.P == 2 && op.elmat && op.elmat_prec == tprec &&
+  if (mode == HPMG_STORED && op.P == 2 && op.elmat && op.elmat_prec == tprec &&
       op.elmat_version == f.state_version) {
     k_elmat_apply<T><<<grid1d(op.E, ELB), ELB * 24, 0, s>>>(op.emap, (const T *)op.elmat, du, ev, op.E, stop);
     hipError_t e2 = hipGetLastError();
@@ -1909,16 +1843,15 @@ static hipError_t jacobian_t(const hpmg_op_s &op, int mode, const double *u, con
   }
   hipError_t e = hipErrorInvalidValue;
 #define X(p, q) \
-  if (op.P == p && op.Q == q) e = jacobian_pq<T, p, q>(op, f, mode, u, du, y, ev, stop, s);
+  if (op.P == p && op.Q == q) e = jacobian_pq<T, p, q>(op, f, mode, u, du, ev, stop, s);
   HPMG_PQ_LIST(X)
 #undef X
-  if (e != hipSuccess || atom) return e;
+  if (e != hipSuccess) return e;
   return assemble_or_dot<T>(op, du, y, pq, stop, s);
 }
 
 hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
                                const double *stop, hipStream_t s) {
-  if (use_atomic_scatter()) return hipErrorInvalidValue;
   if (prec == HPMG_F64)
     return jacobian_t<double>(op, HPMG_STORED, nullptr, (const double *)du, (double *)y, s, pq, stop);
   return jacobian_t<float>(op, HPMG_STORED, nullptr, (const float *)du, (float *)y, s, pq, stop);
