@@ -64,6 +64,11 @@ def time_op(fn, steps, warmup, stream):
     return t0.elapsed_time(t1) / steps  # ms
 
 
+def time_median(fn, steps, warmup, stream, reps=3):
+    """Median over ``reps`` timed loops of ``steps`` calls (after one warm-up loop)."""
+    return float(np.median([time_op(fn, steps, warmup if r == 0 else 1, stream) for r in range(reps)]))
+
+
 def copy_bandwidth(nbytes=2 << 30):
     """Plain streaming kernel of known size (read 2 GiB, write 2 GiB): the achievable
     bandwidth, and the reference that scales the byte counters of a profiled run."""
@@ -129,38 +134,150 @@ def adjoint_bench(steps, warmup, stream):
                        "on [0.5, 2]; one VJP = u_bar, mu_bar, lambda_bar", "dof": 3 * m.n_nodes}
     for prec, ww in (("f64", w), ("f32", w32)):
         for mode in ("stored", "recompute"):
-            t = time_op(lambda: op.residual_vjp(u, ww, mode=mode, precision=prec), steps, warmup, stream)
+            t = time_median(lambda: op.residual_vjp(u, ww, mode=mode, precision=prec), steps, warmup, stream)
             out[f"{prec}_{mode}"] = {"ms": t, "GDoF/s": 3 * m.n_nodes / (t * 1e-3) / 1e9}
     return out
 
 
-def cpu_baseline(wl, target_s=15.0):
-    """The oracle's matrix-free Jacobian apply (dense element tables, FP64, numpy) on a
-    bounded sample of the workload's elements; rate scaled to DoF of the full mesh."""
+def _host_description():
+    import platform
+    info = {"cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
+            "processor": platform.processor() or platform.machine()}
+    try:
+        from threadpoolctl import threadpool_info
+        info["blas"] = [{"api": t.get("internal_api"), "threads": t.get("num_threads")} for t in threadpool_info()]
+    except Exception:  # pragma: no cover
+        info["blas"] = None
+    return info
+
+
+def _submesh(mesh, els, *fields):
+    """The elements ``els`` of ``mesh`` with their own node numbering and the given nodal
+    fields restricted to those nodes (what one CPU worker needs)."""
+    en = mesh.elem_nodes[els]
+    nodes, local = np.unique(en, return_inverse=True)
+    return (mesh.coords[nodes], local.reshape(en.shape)) + tuple(f[nodes] for f in fields)
+
+
+def _oracle_apply_worker(args):
+    """One process of the oracle CPU runs: ``reps`` oracle applies (FP64 numpy, one BLAS
+    thread) on a sub-mesh; returns the seconds it took."""
+    kind, coords, elem_nodes, P, u, du, mu, lam, reps = args
     from threadpoolctl import threadpool_limits
     from oracle import fem
-    from paper_2204_01722_amd import inputs
-    mu, lam = inputs.lame(1.0, 0.3)
-    m = wl.mesh
     with threadpool_limits(limits=1):
-        k = 32
-        d = fem.make_disc(m.coords, m.elem_nodes[:k], m.P)
-        t0 = time.perf_counter()
-        fem.jacobian_apply(d, wl.u_np, wl.du_np, mu, lam, chunk=512)
-        per_el = (time.perf_counter() - t0) / k
-        k = int(min(m.n_elem, max(32, (target_s / 3.0) / per_el)))
-        d = fem.make_disc(m.coords, m.elem_nodes[:k], m.P)
-        reps = max(1, int(round(target_s / (per_el * k))))
+        d = fem.make_disc(coords, elem_nodes, P)
+        if kind == "elmat":
+            Ke = fem.element_matrices(d, u, mu, lam)
+            dof = (3 * elem_nodes[:, :, None] + np.arange(3)[None, None, :]).reshape(len(elem_nodes), -1)
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ye = np.einsum("eij,ej->ei", Ke, du.reshape(-1)[dof])
+                y = np.zeros(du.size)
+                np.add.at(y, dof.reshape(-1), ye.reshape(-1))
+            return time.perf_counter() - t0
         t0 = time.perf_counter()
         for _ in range(reps):
-            fem.jacobian_apply(d, wl.u_np, wl.du_np, mu, lam, chunk=512)
-        dt = (time.perf_counter() - t0) / reps
-    frac = k / m.n_elem
-    rate = wl.dof * frac / dt / 1e9
-    return {"value": rate, "unit": "GDoF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{k} of {m.n_elem} elements of the Q{wl.p} {wl.n}^3 mesh, FP64 Jacobian apply "
-                      f"(dense element tables, numpy, 1 thread), {reps} repeats of {dt:.3f} s; "
-                      f"rate = DoF x sampled fraction / time"}
+            if kind == "jacobian":
+                fem.jacobian_apply(d, u, du, mu, lam, chunk=512)
+            else:
+                fem.residual(d, u, mu, lam, chunk=512)
+        return time.perf_counter() - t0
+
+
+def _oracle_rate(mesh, u, du, kind, seconds, workers=1, reps=2, max_elements=None):
+    """Oracle apply rate (GDoF/s of the full mesh) from a sample of elements sized to take
+    about ``seconds`` per worker (at most ``max_elements`` per worker, the apply then
+    repeated to fill the time); ``workers`` > 1 runs that many spawned processes, each on
+    its own slice of the sample (wall time = the slowest worker)."""
+    import multiprocessing as mp
+    mu, lam = 0.38461538461538464, 0.5769230769230769  # E = 1, nu = 0.3
+    probe = min(mesh.n_elem, 16)
+    c, en, us, dus = _submesh(mesh, np.arange(probe), u, du)
+    per_el = _oracle_apply_worker((kind, c, en, mesh.P, us, dus, mu, lam, 3)) / (3 * probe)
+    k = int(min(mesh.n_elem // workers, max(16, seconds / reps / per_el)))
+    if max_elements is not None and k > max_elements:
+        k = max_elements
+        reps = max(reps, int(seconds / (per_el * k)))
+    slices = [np.arange(w * k, (w + 1) * k) for w in range(workers)]
+    jobs = [(kind,) + _submesh(mesh, sl, u, du)[:2] + (mesh.P,) + _submesh(mesh, sl, u, du)[2:] +
+            (mu, lam, reps) for sl in slices]
+    if workers == 1:
+        dt = _oracle_apply_worker(jobs[0])
+    else:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            dt = max(pool.map(_oracle_apply_worker, jobs))
+    frac = workers * k / mesh.n_elem
+    return {"GDoF/s": 3 * mesh.n_nodes * frac / (dt / reps) / 1e9, "elements": workers * k, "workers": workers,
+            "seconds": dt}
+
+
+def _oracle_tiny_solve():
+    """The first load step of the configuration's p-MG Newton solve on a tiny replica
+    (Q4 -> Q2 -> Q1 on 2^3 elements, x = 0 clamped, x = 1 face displaced by 0.1 = one of
+    five steps of 0.5, FCG with the oracle's V-cycle to 1e-3, Newton to 1e-8), timed on
+    one thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import fem, mg as omg
+    from paper_2204_01722_amd import inputs
+    mu, lam = inputs.lame(1.0, 0.3)
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(2, 4, jitter=0.05, seed=2204)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    orders = [4, 2, 1]
+    topos = [m.elem_nodes] + [inputs.box_topology(m.n, p) for p in orders[1:]]
+    nn = [int(np.prod([p * n + 1 for n in m.n])) for p in orders]
+    masks = [inputs.face_mask(m, faces)] + [inputs.face_mask(None, faces, p=p, n=m.n) for p in orders[1:]]
+    Ps = [omg.prolongation(topos[l - 1], orders[l - 1] + 1, nn[l - 1], topos[l], orders[l] + 1, nn[l])
+          for l in range(1, 3)]
+    seeds = [inputs.rough_seed(nn[l], masks[l], 7 + l) for l in range(2)]
+    lift = inputs.affine_lifting(m, (0.1, 0.0, 0.0))
+    its = []
+
+    def solve(K, rhs):
+        V = omg.VCycle(K, Ps, masks, seeds, degree=3)
+        x, k, _ = omg.fcg(K, lambda v: V(v), rhs, rtol=1e-3)[:3]
+        its.append(k)
+        return x
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        u, hist = omg.newton_load_steps(d, mu, lam, masks[0], lift, 1, solve, rtol=1e-8)
+        dt = time.perf_counter() - t0
+    return {"seconds": dt, "dof": 3 * m.n_nodes, "newton_its": int(sum(hist)), "fcg_its": int(sum(its)),
+            "workload": "first load step of the configuration's solve on a Q4->Q2->Q1 2^3 jittered box: x=0 "
+                        "clamped, x=1 face displaced by 0.1, FCG + oracle V-cycle to 1e-3, Newton to 1e-8"}
+
+
+def cpu_baseline(wl, seconds=6.0):
+    """The FP64 oracle (dense element tables, numpy) timed on this host: the Jacobian
+    apply on bounded samples of the Q4 34^3 and Q2 43^3 workloads on one thread and on
+    all allowed cores (at most 16 processes, one BLAS thread each), the residual, the Q2
+    apply from assembled element matrices, and the p-MG Newton solve on a tiny replica."""
+    from paper_2204_01722_amd import inputs
+    host = _host_description()
+    cores = max(1, min(16, host["affinity"]))
+    legs = {}
+    print("[bench] CPU oracle: Q4 Jacobian", file=sys.stderr, flush=True)
+    legs["q4_jacobian_1thread"] = _oracle_rate(wl.mesh, wl.u_np, wl.du_np, "jacobian", seconds)
+    legs["q4_jacobian_all_cores"] = _oracle_rate(wl.mesh, wl.u_np, wl.du_np, "jacobian", seconds, workers=cores)
+    legs["q4_residual_1thread"] = _oracle_rate(wl.mesh, wl.u_np, wl.du_np, "residual", seconds / 2)
+    print("[bench] CPU oracle: Q2", file=sys.stderr, flush=True)
+    m2 = inputs.box_mesh(43, 2, jitter=0.05, seed=2204)
+    u2, du2 = inputs.stretch_field(m2, 1.3), inputs.random_vector(m2.n_nodes, 3)
+    legs["q2_jacobian_1thread"] = _oracle_rate(m2, u2, du2, "jacobian", seconds / 2)
+    legs["q2_jacobian_all_cores"] = _oracle_rate(m2, u2, du2, "jacobian", seconds / 2, workers=cores)
+    legs["q2_element_matrix_apply_1thread"] = _oracle_rate(m2, u2, du2, "elmat", seconds / 2, reps=4,
+                                                           max_elements=2000)
+    legs["q4_element_matrix_apply"] = "skipped: 375 x 375 element matrices of 39,304 elements need 44 GB"
+    print("[bench] CPU oracle: tiny p-MG solve", file=sys.stderr, flush=True)
+    legs["pmg_newton_tiny_replica_1thread"] = _oracle_tiny_solve()
+    main = legs["q4_jacobian_all_cores"]
+    return {"value": main["GDoF/s"], "unit": "GDoF/s", "cores": main["workers"], "kind": "oracle",
+            "sample": f"{main['elements']} of {wl.mesh.n_elem} elements of the Q{wl.p} {wl.n}^3 mesh, FP64 "
+                      f"Jacobian apply (dense element tables, numpy), {main['workers']} processes with one "
+                      f"BLAS thread each; rate = DoF x sampled fraction / wall time",
+            "host": host, "legs": legs}
 
 
 def pmg_solve(n=16, p=4, steps=5, total_disp=0.5, inclusions=False, monitor=False, lbfgs=True,
@@ -267,6 +384,9 @@ def main():
                     help="only the inexact-Newton forms (FCG to 1e-3), not the FCG-to-1e-8 ones")
     ap.add_argument("--pmg-newton-only", action="store_true",
                     help="only the Galerkin Newton solves (FP64 and mixed): no rediscretised or L-BFGS legs")
+    ap.add_argument("--profile-applies", action="store_true",
+                    help="only run the stored Jacobian applies (Q4 34^3 and Q2 43^3, FP64 and FP32) --steps "
+                         "times each, for a profiler")
     ap.add_argument("--pmg-strain", type=float, default=0.10,
                     help="compressive strain of the multiscale block (0.10: solved on every mesh up to 80^3)")
     args = ap.parse_args()
@@ -280,6 +400,19 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.profile_applies:
+        for n, p in ((34, 4), (43, 2)):
+            wl = Workload(n, p)
+            for prec in ("f64", "f32"):
+                ms = time_op(wl.apply(prec, "stored"), args.steps, args.warmup, stream)
+                print(f"[profile] Q{p} {n}^3 {prec} stored: {args.steps} applies, {ms * 1000:.1f} us each",
+                      file=sys.stderr, flush=True)
+            del wl
+            torch.cuda.empty_cache()
+        # a plain copy of known size (2 GiB read, 2 GiB written): the reference that
+        # scales the HBM byte counters
+        print(f"[profile] copy: {copy_bandwidth():.1f} GB/s", file=sys.stderr, flush=True)
+        return
     if args.pmg_only:
         if args.pmg_inclusions:
             res = pmg_solve(n=args.pmg_n, steps=10, total_disp=-args.pmg_strain, inclusions=True,
@@ -299,19 +432,20 @@ def main():
     achieved = nbytes / (ms * 1e-3) / 1e9
     print(f"[bench] Q4 f64 stored: {ms:.4f} ms, {value:.2f} GDoF/s", file=sys.stderr, flush=True)
 
-    variants = {}
+    # the same loop repeated: the spread of the headline on this machine
+    variants = {"headline_repeats_ms": [time_op(q4.apply("f64", "stored"), args.steps, 1, stream) for _ in range(4)]}
     if not args.only_headline:
         for prec, mode in (("f32", "stored"), ("f64", "recompute"), ("f32", "recompute")):
-            t = time_op(q4.apply(prec, mode), args.steps, args.warmup, stream)
+            t = time_median(q4.apply(prec, mode), args.steps, args.warmup, stream)
             variants[f"q4_{prec}_{mode}"] = {"ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9}
-        t = time_op(q4.residual(), max(5, args.steps // 5), 2, stream)
+        t = time_median(q4.residual(), max(5, args.steps // 5), 2, stream)
         variants["q4_residual_f64"] = {"ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9}
         variants["q4_f32_stored"]["hbm_frac"] = (algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 4) /
                                                  (variants["q4_f32_stored"]["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS)
         # the initial-configuration (S(E)) forms of the same operator: 19 and 26 scalars
         q4.op.state_initial(q4.u)
         for mode, ns in (("initial_native", 19), ("initial_tuned", 26), ("current_20", 20)):
-            t = time_op(q4.apply("f64", mode), args.steps, args.warmup, stream)
+            t = time_median(q4.apply("f64", mode), args.steps, args.warmup, stream)
             variants[f"q4_f64_{mode}"] = {
                 "ms": t, "GDoF/s": q4.dof / (t * 1e-3) / 1e9, "scalars_per_point": ns,
                 "hbm_frac": algorithmic_bytes(q4.E, q4.P, q4.Q, q4.N, 8, nstate=ns) / (t * 1e-3) / 1e9 /
@@ -319,7 +453,7 @@ def main():
         print("[bench] building Q2 43^3 workload", file=sys.stderr, flush=True)
         q2 = Workload(43, 2)
         for prec, mode in (("f64", "stored"), ("f32", "stored"), ("f64", "recompute")):
-            t = time_op(q2.apply(prec, mode), args.steps, args.warmup, stream)
+            t = time_median(q2.apply(prec, mode), args.steps, args.warmup, stream)
             v = {"ms": t, "GDoF/s": q2.dof / (t * 1e-3) / 1e9}
             if mode == "stored":
                 v["hbm_frac"] = (algorithmic_bytes(q2.E, q2.P, q2.Q, q2.N, 8 if prec == "f64" else 4) /
@@ -331,7 +465,7 @@ def main():
             print(f"[bench] building Q{p} {n}^3 workload (cache-busting)", file=sys.stderr, flush=True)
             wl = Workload(n, p)
             for prec in ("f64", "f32"):
-                t = time_op(wl.apply(prec, "stored"), max(10, args.steps // 2), 3, stream)
+                t = time_median(wl.apply(prec, "stored"), max(10, args.steps // 2), 3, stream)
                 variants[f"q{p}_{n}cubed_{prec}_stored"] = {
                     "ms": t, "dof": wl.dof, "GDoF/s": wl.dof / (t * 1e-3) / 1e9,
                     "hbm_frac": algorithmic_bytes(wl.E, wl.P, wl.Q, wl.N, 8 if prec == "f64" else 4) /
