@@ -312,9 +312,11 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
  * Step k = 1..n_steps adds lift / n_steps to u (lift holds the full imposed displacement
  * on constrained components and an extension elsewhere) and iterates on
  * F(u) = r(u) - (k / n_steps) f_ext (f_ext: external dead load from hpmg_external_load,
- * or NULL) until ||F(u)|| <= rtol ||F(u_start)||.  The first correction of a load increment uses the
- * tangent of the previous converged state (an Euler predictor), later ones the tangent
- * at the current iterate.  Linear solves: FCG + V-cycle to lin_rtol (a negative-
+ * or NULL) until ||F(u)|| <= rtol ||F(u_start)||.  An increment starts from the secant
+ * extrapolation of the last two converged load levels when there are two (predictor = 1),
+ * else from the previous converged state plus the lifted increment, whose first
+ * correction uses the tangent of that previous state (an Euler predictor); later
+ * corrections use the tangent at the current iterate.  Linear solves: FCG + V-cycle to lin_rtol (a negative-
  * curvature breakdown truncates the solve and the line search takes the direction found
  * so far).  A step length whose point has an inverted element or a non-finite residual
  * is halved (at most 6 times).  A load increment whose Newton solve fails (iteration
@@ -337,6 +339,10 @@ typedef struct {
                        relative residual, FCG iterations and outcome, step length */
   int max_total_newton; /* (200) Newton iterations of the whole solve, retries included */
   int max_total_krylov; /* (20000) FCG iterations of the whole solve, retries included */
+  int predictor;        /* (1) 1: once two load levels have converged, an increment starts
+                           from their secant extrapolation (tangent at that start); it falls
+                           back to the lifted start when that point has an inverted element.
+                           0: always the lifted start with the Euler predictor */
 } hpmg_newton_params;
 void hpmg_newton_default_params(hpmg_newton_params *p);
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext,

@@ -42,7 +42,7 @@ class MGParams(C.Structure):
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_newton", C.c_int), ("lin_rtol", C.c_double),
                 ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int),
-                ("max_total_newton", C.c_int), ("max_total_krylov", C.c_int)]
+                ("max_total_newton", C.c_int), ("max_total_krylov", C.c_int), ("predictor", C.c_int)]
 
 
 class LbfgsParams(C.Structure):
@@ -526,7 +526,8 @@ class PMG:
         return x, int(its.value), float(rel.value)
 
     def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
-               line_search=True, monitor=False, f_ext=None, max_total_newton=None, max_total_krylov=None):
+               line_search=True, monitor=False, f_ext=None, max_total_newton=None, max_total_krylov=None,
+               predictor=None):
         _vec(u, self.levels[0].n_nodes, torch.float64, self.levels[0].device, "u")
         lift = self._fine_vec(lift, "lift")
         f_ext = None if f_ext is None else self._fine_vec(f_ext, "f_ext")
@@ -539,6 +540,8 @@ class PMG:
             prm.max_total_newton = int(max_total_newton)
         if max_total_krylov is not None:
             prm.max_total_krylov = int(max_total_krylov)
+        if predictor is not None:
+            prm.predictor = int(bool(predictor))
         stats = (C.c_double * (4 + n_steps))()
         st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift),
                                      None if f_ext is None else _p(f_ext), int(n_steps),

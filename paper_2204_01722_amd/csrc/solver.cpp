@@ -45,7 +45,7 @@ struct hpmg_mg_s {
   double *host = nullptr;    // pinned host mirror (SC_N)
   // fine FP64 vectors for the Krylov and Newton drivers
   double *fr = nullptr, *fr2 = nullptr, *fz = nullptr, *fp = nullptr, *fq = nullptr;
-  double *nF = nullptr, *ndu = nullptr, *nut = nullptr, *nu0 = nullptr;
+  double *nF = nullptr, *ndu = nullptr, *nut = nullptr, *nu0 = nullptr, *nup = nullptr;
   int last_coarse_its = 0;
   int setup_done = 0;
   // Order-1 Galerkin coarsest level assembled into 3 x 3 node blocks, sliced ELL:
@@ -113,6 +113,7 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   mg->ndu = reinterpret_cast<double *>(take(nf));
   mg->nut = reinterpret_cast<double *>(take(nf));
   mg->nu0 = reinterpret_cast<double *>(take(nf));
+  mg->nup = reinterpret_cast<double *>(take(nf));
   return o;
 }
 
@@ -667,6 +668,7 @@ void hpmg_newton_default_params(hpmg_newton_params *p) {
   p->monitor = 0;
   p->max_total_newton = 200;
   p->max_total_krylov = 20000;
+  p->predictor = 1;
 }
 
 // Iteration budget of a whole Newton solve (every load step and retry together).
@@ -689,16 +691,18 @@ static int store_state(hpmg_op fine, hpmg_mg_s *mg, const double *u, hipStream_t
   return HPMG_OK;
 }
 
-// Newton solve at one load level (Section III-A).  On entry u holds the previous
-// converged state plus the load increment and the stored linearisation belongs to that
-// previous state: the first correction is taken with that tangent (an Euler predictor
-// for the increment), later ones with the tangent at the current iterate.  Every
+// Newton solve at one load level (Section III-A).  On entry u holds the start of the
+// increment.  With state_at_start the stored linearisation belongs to u (a secant-
+// extrapolated start); otherwise u is the previous converged state plus the lifted load
+// increment and the stored linearisation belongs to that previous state (saved in nu0):
+// the first correction is taken with that tangent (an Euler predictor for the
+// increment).  Later corrections use the tangent at the current iterate.  Every
 // accepted point is checked for inverted elements and non-finite values; the step is
 // halved (at most 6 times) until it passes.  Returns HPMG_OK on convergence, else an
 // error that tells the caller to cut the increment.
 static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *f_ext,
                           const hpmg_newton_params *prm, const double *const *seeds, void *stream, double load,
-                          NewtonBudget *budget, int *its_out, int *lin_out, double *rel_out) {
+                          bool state_at_start, NewtonBudget *budget, int *its_out, int *lin_out, double *rel_out) {
   int st;
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
@@ -725,7 +729,7 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *
     budget->newton_left--;
     // the fine state belongs to the previous converged point in the predictor
     // iteration (saved in nu0), to u afterwards
-    if (has_redisc(mg) && (st = set_state(mg, its == 0 ? mg->nu0 : u, s))) return st;
+    if (has_redisc(mg) && (st = set_state(mg, its == 0 && !state_at_start ? mg->nu0 : u, s))) return st;
     if ((st = do_setup(mg, seeds, s))) return st;
     HPMG_HIP(launch_waxpby(HPMG_F64, n, -1.0, F, 0.0, F, ut, s));
     HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
@@ -803,6 +807,13 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, c
   for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;
   int total_newton = 0, total_lin = 0, cuts = 0;
   NewtonBudget budget{prm->max_total_newton, prm->max_total_krylov};
+  // Secant predictor: once two converged load levels are known (nup, then u), a new
+  // increment starts from their linear extrapolation, which carries the previous
+  // increment's deformation pattern (for stiff inclusions: the soft matrix takes the
+  // compression) instead of the affine lifting; constrained components still receive
+  // exactly the prescribed increment.
+  bool have_prev = false;
+  double prev_inc = 0.0;
   double final_rel = 0.0;
   // Load increments of 1/n_steps; an increment whose Newton solve fails is retried from
   // the previous converged state in halves (at most 6 halvings in a row); after a
@@ -823,18 +834,41 @@ int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, c
         state_at_u = true;
       }
       HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, u, 0.0, u, mg->nu0, s));
-      HPMG_HIP(launch_axpby(HPMG_F64, n, inc / n_steps, lift, 1.0, u, s));
+      bool extrapolated = false;
+      if (prm->predictor && have_prev) {
+        const double r = inc / prev_inc;
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0 + r, mg->nu0, -r, mg->nup, u, s));
+        double f_start = 0.0;
+        if ((st = store_state(fine, mg, u, s, &f_start))) return st;
+        unsigned fl = 0;
+        if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
+        extrapolated = std::isfinite(f_start) && !(fl & (HPMG_FLAG_NONPOSITIVE_J | HPMG_FLAG_NONFINITE));
+        if (!extrapolated) {  // inadmissible start: back to the lifted start from nu0
+          HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, u, s));
+          if ((st = store_state(fine, mg, u, s, &f_start))) return st;
+          if ((st = hpmg_op_query_flags(fine, stream, &fl))) return st;
+        }
+        state_at_u = true;
+      }
+      if (!extrapolated) HPMG_HIP(launch_axpby(HPMG_F64, n, inc / n_steps, lift, 1.0, u, s));
+      if (prm->monitor)
+        std::fprintf(stderr, "[newton] load %.6f start: %s\n", (step + done + inc) / n_steps,
+                     extrapolated ? "secant extrapolation" : "lifted increment");
       int its = 0;
       double rel = 0.0;
-      st = newton_at_load(fine, mg, u, f_ext, prm, seeds, stream, (step + done + inc) / n_steps, &budget, &its,
-                          &total_lin, &rel);
+      st = newton_at_load(fine, mg, u, f_ext, prm, seeds, stream, (step + done + inc) / n_steps, extrapolated,
+                          &budget, &its, &total_lin, &rel);
       if (st && prm->monitor)
         std::fprintf(stderr, "[newton] load %.6f failed (%s); halving the increment\n", (step + done + inc) / n_steps,
                      hpmg_last_error());
       total_newton += its;
       stats[4 + step] += its;
       if (st == HPMG_OK) {
-        state_at_u = its > 0;  // with no iteration the stored state is still the previous one
+        // with no iteration from a lifted start the stored state is still the previous one
+        state_at_u = its > 0 || extrapolated;
+        HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, mg->nu0, 0.0, mg->nu0, mg->nup, s));
+        have_prev = true;
+        prev_inc = inc;
         done += inc;
         final_rel = rel;
         dt = std::min(1.0, 2.0 * inc);
