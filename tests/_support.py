@@ -38,6 +38,22 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def rel_max(a, b):
+    """Max-norm relative error ``max|a - b| / max|b|``."""
+    a = np.asarray(a, np.float64).reshape(-1)
+    b = np.asarray(b, np.float64).reshape(-1)
+    mb = np.abs(b).max() if b.size else 0.0
+    return np.abs(a - b).max() / (mb if mb > 0 else 1.0) if a.size else 0.0
+
+
+def report(name, got, ref):
+    """Relative errors of ``got`` against ``ref`` in the 2-norm (returned, asserted by the
+    caller) and the max-norm (printed beside it)."""
+    e2, einf = rel(got, ref), rel_max(got, ref)
+    print(f"  {name}: rel 2-norm {e2:.2e}, rel max-norm {einf:.2e}", flush=True)
+    return e2
+
+
 def t2n(t):
     return t.detach().double().cpu().numpy()
 

@@ -4,7 +4,7 @@ FP64 results must match to 1e-12 relative (2-norm), FP32 applies to 1e-5."""
 import numpy as np
 import pytest
 
-from _support import LAM, MU, ensure_built, gpu_available, incident_elements, print_case, rel, t2n
+from _support import LAM, MU, ensure_built, gpu_available, incident_elements, print_case, rel, report, t2n
 from oracle import basis as obasis
 from oracle import fem, mg as omg
 from paper_2204_01722_amd import inputs
@@ -77,18 +77,18 @@ def test_residual_and_jacobian(n, p, q, faces):
     ut, dut = _dev(u), _dev(du)
     r = op.residual(ut, store_state=True)
     r_ref = fem.residual(d, u, MU, LAM, mask)
-    assert rel(t2n(r), r_ref) < TOL64
+    assert report("residual", t2n(r), r_ref) < TOL64
     y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
     y = op.jacobian(dut, "f64", "stored")
-    assert rel(t2n(y), y_ref) < TOL64
+    assert report("J du FP64 stored", t2n(y), y_ref) < TOL64
     y = op.jacobian(dut, "f64", "recompute", u=ut)
-    assert rel(t2n(y), y_ref) < TOL64
+    assert report("J du FP64 recompute", t2n(y), y_ref) < TOL64
     op.state_cast_f32()
     y32 = op.jacobian(dut.float(), "f32", "stored")
     assert y32.dtype == torch.float32
-    assert rel(t2n(y32), y_ref) < TOL32
+    assert report("J du FP32 stored", t2n(y32), y_ref) < TOL32
     y32 = op.jacobian(dut.float(), "f32", "recompute", u=ut)
-    assert rel(t2n(y32), y_ref) < TOL32
+    assert report("J du FP32 recompute", t2n(y32), y_ref) < TOL32
     if mask is not None:
         mb = mask.astype(bool)
         assert np.all(t2n(y)[mb] == du[mb])
@@ -275,12 +275,20 @@ def test_full_size_sampled(n, p):
     assert op.query_flags() == 0
     rng = np.random.default_rng(99)
     nodes = rng.choice(m.n_nodes, 48, replace=False)
+    # plus nodes of the elements where each XCD's contiguous tile range starts (the tiles
+    # are split in 8 ranges) and of the last element (the last, possibly ragged, tile)
+    info = op.info()
+    ET, tiles = info["elems_per_tile"], info["tiles"]
+    starts = [min(m.n_elem - 1, ((x * (tiles // 8) + min(x, tiles % 8)) * ET)) for x in range(8)]
+    for e in starts + [m.n_elem - 1]:
+        nodes = np.append(nodes, m.elem_nodes[e][[0, m.P ** 3 // 2, m.P ** 3 - 1]])
+    nodes = np.unique(nodes)
     els = incident_elements(m.elem_nodes, nodes)
     d = fem.make_disc(m.coords, m.elem_nodes[els], m.P)
     r_ref = fem.residual(d, u, MU, LAM)[nodes]
     y_ref = fem.jacobian_apply(d, u, du, MU, LAM)[nodes]
-    assert rel(r[nodes], r_ref) < TOL64
-    assert rel(y[nodes], y_ref) < TOL64
+    assert report(f"residual at {len(nodes)} sampled nodes", r[nodes], r_ref) < TOL64
+    assert report(f"J du at {len(nodes)} sampled nodes", y[nodes], y_ref) < TOL64
     torch.cuda.synchronize()
 
 
