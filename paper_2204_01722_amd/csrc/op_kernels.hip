@@ -1635,7 +1635,9 @@ __global__ __launch_bounds__(256) void k_assemble_staged(int64_t N, const int32_
                                                          const uint8_t *__restrict__ mask, const T *__restrict__ src,
                                                          T fill, T *__restrict__ y) {
   __shared__ T buf[3 * 256];
-  const int64_t n0 = (int64_t)blockIdx.x * 256, n = n0 + threadIdx.x;
+  // consecutive node ranges stay on one XCD (see xcd_tile): neighbouring nodes share
+  // elements, so their records meet in the same L2
+  const int64_t n0 = xcd_tile() * 256, n = n0 + threadIdx.x;
   if (n < N) {
     const int32_t k0 = off[n], k1 = off[n + 1];
     T a0 = 0, a1 = 0, a2 = 0;
