@@ -297,7 +297,7 @@ def cpu_baseline(wl, seconds=6.0):
 
 
 def pmg_solve(n=16, p=4, steps=5, total_disp=0.5, inclusions=False, monitor=False, lbfgs=True,
-              rediscretize=True, exact=True):
+              rediscretize=True, exact=True, prime_s=0.3):
     """FP64 vs mixed-precision p-MG Newton solve (Q4 -> Q2 -> Q1, Chebyshev degree 3,
     order-1 coarse level solved by Jacobi-PCG to 1e-3, Newton to 1e-8).  Default: x = 0
     clamped, x = 1 face displaced by `total_disp` along x in `steps` load steps.  With
@@ -334,7 +334,7 @@ def pmg_solve(n=16, p=4, steps=5, total_disp=0.5, inclusions=False, monitor=Fals
         mg = PMG(H.ops, precision=prec, cheb_degree=3, coarse_rtol=1e-3)
         u = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
         seeds = H.seeds(7)
-        prime(lambda: H.fine.residual(u, store_state=False), 0.3)
+        prime(lambda: H.fine.residual(u, store_state=False), prime_s)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if quasi_newton:
@@ -436,10 +436,12 @@ def main():
         if args.pmg_inclusions:
             res = pmg_solve(n=args.pmg_n, steps=10, total_disp=-args.pmg_strain, inclusions=True,
                             monitor=args.pmg_monitor, lbfgs=not args.pmg_newton_only,
-                            rediscretize=not args.pmg_newton_only, exact=not args.pmg_inexact_only)
+                            rediscretize=not args.pmg_newton_only, exact=not args.pmg_inexact_only,
+                            prime_s=min(0.3, args.prime))
         else:
             res = pmg_solve(n=args.pmg_n, monitor=args.pmg_monitor, lbfgs=not args.pmg_newton_only,
-                            rediscretize=not args.pmg_newton_only, exact=not args.pmg_inexact_only)
+                            rediscretize=not args.pmg_newton_only, exact=not args.pmg_inexact_only,
+                            prime_s=min(0.3, args.prime))
         print(json.dumps({"pmg_solve": res}))
         return
 
@@ -501,7 +503,7 @@ def main():
     solve = None
     if not args.no_solve and not args.only_headline:
         print("[bench] p-MG solve FP64 vs mixed", file=sys.stderr, flush=True)
-        solve = pmg_solve(n=args.pmg_n)
+        solve = pmg_solve(n=args.pmg_n, prime_s=min(0.3, args.prime))
 
     cpu = None
     if not args.no_cpu:
