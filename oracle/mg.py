@@ -219,17 +219,22 @@ class VCycle:
         return self.cycle(0, np.asarray(r, np.float64).reshape(-1))
 
 
-def fcg(A, prec, b, rtol=1e-8, maxit=500, x0=None):
-    """Flexible CG (Polak-Ribiere beta) for ``A x = b``.  Stops when
-    ``||b - A x||_2 <= rtol ||b - A x0||_2``.  Returns ``x, its, final_relres``."""
+def fcg(A, prec, b, rtol=1e-8, maxit=500, x0=None, norm="2"):
+    """Flexible CG (Polak-Ribiere beta) for ``A x = b``.  ``norm="2"`` stops when
+    ``||b - A x||_2 <= rtol ||b - A x0||_2``; ``norm="natural"`` measures the residual
+    in the natural norm of the preconditioned system (Section III-A),
+    ``sqrt(r^T prec(r))``, relative to its value at x0.  Returns
+    ``x, its, final_relres``."""
+    if norm not in ("2", "natural"):
+        raise ValueError(norm)
     x = np.zeros_like(b) if x0 is None else x0.copy()
     r = b - A @ x
-    r0 = np.linalg.norm(r)
+    z = prec(r)
+    rz = r @ z
+    r0 = np.sqrt(abs(rz)) if norm == "natural" else np.linalg.norm(r)
     if r0 == 0.0:
         return x, 0, 0.0
-    z = prec(r)
     p = z.copy()
-    rz = r @ z
     its = 0
     rel = 1.0
     while its < maxit:
@@ -238,32 +243,37 @@ def fcg(A, prec, b, rtol=1e-8, maxit=500, x0=None):
         x += a * p
         r_new = r - a * q
         its += 1
-        rel = np.linalg.norm(r_new) / r0
+        z = prec(r_new)
+        rz_new = r_new @ z
+        rel = (np.sqrt(abs(rz_new)) if norm == "natural" else np.linalg.norm(r_new)) / r0
         if rel <= rtol:
             break
-        z = prec(r_new)
         beta = (z @ (r_new - r)) / rz
-        rz = r_new @ z
+        rz = rz_new
         p = z + beta * p
         r = r_new
     return x, its, rel
 
 
-def fcg_truncated(A, prec, b, rtol=1e-8, maxit=500):
-    """Flexible CG as ``fcg`` from x0 = 0, stopped at a direction of non-positive
+def fcg_truncated(A, prec, b, rtol=1e-8, maxit=500, norm="2"):
+    """Flexible CG as ``fcg`` (same ``norm`` choice) from x0 = 0, stopped at a direction of non-positive
     curvature (p^T A p <= 0, possible when the Newton tangent is indefinite): the iterate
     reached so far is returned, or the preconditioned residual when it happens before the
     first step, so that a Newton step can still move along a descent direction (the
     truncated-Newton treatment of negative curvature).  Returns
     ``x, its, final_relres, broke``."""
+    if norm not in ("2", "natural"):
+        raise ValueError(norm)
     x = np.zeros_like(b)
     r = b.copy()
-    r0 = np.linalg.norm(r)
-    if r0 == 0.0:
+    if not np.any(r):
         return x, 0, 0.0, False
     z = prec(r)
-    p = z.copy()
     rz = r @ z
+    r0 = np.sqrt(abs(rz)) if norm == "natural" else np.linalg.norm(r)
+    if r0 == 0.0:
+        return x, 0, 0.0, False
+    p = z.copy()
     its, rel = 0, 1.0
     while its < maxit:
         q = A @ p
@@ -276,12 +286,13 @@ def fcg_truncated(A, prec, b, rtol=1e-8, maxit=500):
         x += a * p
         r_new = r - a * q
         its += 1
-        rel = np.linalg.norm(r_new) / r0
+        z = prec(r_new)
+        rz_new = r_new @ z
+        rel = (np.sqrt(abs(rz_new)) if norm == "natural" else np.linalg.norm(r_new)) / r0
         if rel <= rtol:
             break
-        z = prec(r_new)
         beta = (z @ (r_new - r)) / rz
-        rz = r_new @ z
+        rz = rz_new
         p = z + beta * p
         r = r_new
     return x, its, rel, False

@@ -42,7 +42,8 @@ class MGParams(C.Structure):
 class NewtonParams(C.Structure):
     _fields_ = [("rtol", C.c_double), ("max_newton", C.c_int), ("lin_rtol", C.c_double),
                 ("lin_maxit", C.c_int), ("line_search", C.c_int), ("monitor", C.c_int),
-                ("max_total_newton", C.c_int), ("max_total_krylov", C.c_int), ("predictor", C.c_int)]
+                ("max_total_newton", C.c_int), ("max_total_krylov", C.c_int), ("predictor", C.c_int),
+                ("lin_norm", C.c_int)]
 
 
 class LbfgsParams(C.Structure):
@@ -527,7 +528,12 @@ class PMG:
 
     def newton(self, u, lift, n_steps, seeds, rtol=1e-8, max_newton=20, lin_rtol=1e-3, lin_maxit=500,
                line_search=True, monitor=False, f_ext=None, max_total_newton=None, max_total_krylov=None,
-               predictor=None):
+               predictor=None, lin_norm="2"):
+        """Newton load stepping (``u`` FP64 [N][3], updated in place).  ``lin_norm``: the
+        FCG stopping norm, "2" for the residual 2-norm, "natural" for sqrt(r^T M^-1 r)
+        with M^-1 the V-cycle.  Returns ``u`` and a statistics dict."""
+        if lin_norm not in ("2", "natural"):
+            raise ValueError(f"lin_norm must be '2' or 'natural', got {lin_norm!r}")
         _vec(u, self.levels[0].n_nodes, torch.float64, self.levels[0].device, "u")
         lift = self._fine_vec(lift, "lift")
         f_ext = None if f_ext is None else self._fine_vec(f_ext, "f_ext")
@@ -542,6 +548,7 @@ class PMG:
             prm.max_total_krylov = int(max_total_krylov)
         if predictor is not None:
             prm.predictor = int(bool(predictor))
+        prm.lin_norm = 1 if lin_norm == "natural" else 0
         stats = (C.c_double * (4 + n_steps))()
         st = lib().hpmg_newton_solve(self.levels[0].h, self.h, _p(u), _p(lift),
                                      None if f_ext is None else _p(f_ext), int(n_steps),

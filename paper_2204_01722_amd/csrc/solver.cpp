@@ -422,8 +422,11 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
   return HPMG_OK;
 }
 
+// natural: stop on the preconditioned (natural) norm sqrt(r^T M^-1 r) relative to its
+// start value instead of the 2-norm of r; the V-cycle of an iteration's new residual is
+// then applied before the test (it is the next iteration's anyway).
 int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol, int maxit, int *its_out,
-           double *rel_out, hipStream_t s) {
+           double *rel_out, hipStream_t s, bool natural) {
   int st;
   const int64_t n = mg->lv[0].n;
   double *sc = mg->scal;
@@ -439,6 +442,12 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
   if ((st = vcycle(mg, r, z, s))) return st;
   HPMG_HIP(launch_dot(HPMG_F64, n, r, z, mg->red, sc + FCG_RZ, s));
   HPMG_HIP(launch_waxpby(HPMG_F64, n, 1.0, z, 0.0, z, p, s));
+  double nat0 = 0.0;
+  if (natural) {
+    if ((st = read_scalars(mg, FCG_RZ + 1, s))) return st;
+    nat0 = std::sqrt(std::fabs(mg->host[FCG_RZ]));
+    if (!(nat0 > 0.0)) return HPMG_OK;
+  }
   // alpha and beta are formed on the device from the dot products; the host reads the
   // scalars once per iteration, for the convergence and breakdown tests.
   int its = 0;
@@ -447,6 +456,11 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
     HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, p, q, s));
     HPMG_HIP(launch_dot(HPMG_F64, n, p, q, mg->red, sc + FCG_PQ, s));
     HPMG_HIP(launch_fcg_update(n, sc, its, p, q, x, r, rn, mg->red, s));
+    if (natural) {
+      // z = M^-1 rn and z.rn (the natural norm squared), z.r for the next direction
+      if ((st = vcycle(mg, rn, z, s))) return st;
+      HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));
+    }
     if ((st = read_scalars(mg, FCG_RZ + 2, s))) return st;
     if (mg->host[FCG_BRK] != 0.0) {
       // Negative curvature (or a non-finite preconditioned residual): stop here, x as it
@@ -458,10 +472,12 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
       return fail(HPMG_ERR_BREAKDOWN, "fcg: p^T A p <= 0");
     }
     ++its;
-    rel = std::sqrt(mg->host[FCG_RR]) / r0;
+    rel = natural ? std::sqrt(std::fabs(mg->host[FCG_ZRN])) / nat0 : std::sqrt(mg->host[FCG_RR]) / r0;
     if (rel <= rtol) break;
-    if ((st = vcycle(mg, rn, z, s))) return st;
-    HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));  // z.rn, z.r
+    if (!natural) {
+      if ((st = vcycle(mg, rn, z, s))) return st;
+      HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));  // z.rn, z.r
+    }
     HPMG_HIP(launch_fcg_dir(n, sc, its - 1, z, p, s));
     std::swap(r, rn);
   }
@@ -655,7 +671,7 @@ int hpmg_fcg_solve(hpmg_op fine, hpmg_mg mg, const double *b, double *x, double 
   if (!b || !x || !its || !relres) return fail(HPMG_ERR_ARG, "fcg_solve: null argument");
   if (!mg->setup_done) return fail(HPMG_ERR_ARG, "fcg_solve: call mg_setup first");
   if (!(rtol > 0.0) || maxit < 1) return fail(HPMG_ERR_ARG, "fcg_solve: bad tolerance");
-  return do_fcg(fine, mg, b, x, rtol, maxit, its, relres, S(stream));
+  return do_fcg(fine, mg, b, x, rtol, maxit, its, relres, S(stream), false);
 }
 
 void hpmg_newton_default_params(hpmg_newton_params *p) {
@@ -669,6 +685,7 @@ void hpmg_newton_default_params(hpmg_newton_params *p) {
   p->max_total_newton = 200;
   p->max_total_krylov = 20000;
   p->predictor = 1;
+  p->lin_norm = 0;
 }
 
 // Iteration budget of a whole Newton solve (every load step and retry together).
@@ -735,7 +752,8 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *
     HPMG_HIP(launch_init_bc(HPMG_F64, n / 3, nullptr, nullptr, du, s));
     int lits = 0;
     double lrel = 0.0;
-    st = do_fcg(fine, mg, ut, du, prm->lin_rtol, std::min(prm->lin_maxit, budget->krylov_left), &lits, &lrel, s);
+    st = do_fcg(fine, mg, ut, du, prm->lin_rtol, std::min(prm->lin_maxit, budget->krylov_left), &lits, &lrel, s,
+                prm->lin_norm == 1);
     *lin_out += lits;
     budget->krylov_left -= lits;
     if (st && st != HPMG_ERR_NOT_CONVERGED && st != HPMG_ERR_BREAKDOWN) return st;

@@ -193,6 +193,34 @@ def test_fcg_matches_direct_solve():
     assert its < 100
 
 
+@pytest.mark.parametrize("solver", ["fcg", "fcg_truncated"])
+def test_fcg_natural_norm_is_the_preconditioned_residual_norm(solver):
+    """The natural-norm stop (Section III-A): the reported relative residual is
+    sqrt(r^T M^-1 r) / sqrt(b^T M^-1 b) of the returned iterate, with r recomputed from
+    x (here M^-1 is a Jacobi preconditioner, so the norm is a weighted 2-norm that can be
+    formed without the solver), and the solve stops at the first iteration that meets
+    the tolerance."""
+    mf, maskf, V = _two_level(amplitude=0.0)
+    A = V.ops[0]
+    fr = 1.0 - maskf.reshape(-1)
+    dinv = 1.0 / A.diagonal()
+    M = lambda v: dinv * v  # noqa: E731
+    rng = np.random.default_rng(3)
+    b = rng.normal(size=A.shape[0]) * fr
+    nat = lambda v: np.sqrt(np.sum(dinv * v * v))  # noqa: E731
+    run = getattr(mg, solver)
+    x, its, rel = run(A, M, b, rtol=1e-4, maxit=500, norm="natural")[:3]
+    assert its > 3
+    assert rel <= 1e-4
+    assert abs(rel - nat(b - A @ x) / nat(b)) <= 1e-9 * rel
+    x1, its1, rel1 = run(A, M, b, rtol=1e-4, maxit=its - 1, norm="natural")[:3]
+    assert its1 == its - 1 and rel1 > 1e-4
+    assert abs(rel1 - nat(b - A @ x1) / nat(b)) <= 1e-9 * rel1
+    # the 2-norm stop measures something else: its reported value is ||r||_2 / ||b||_2
+    x2, its2, rel2 = run(A, M, b, rtol=1e-4, maxit=500)[:3]
+    assert abs(rel2 - np.linalg.norm(b - A @ x2) / np.linalg.norm(b)) <= 1e-9 * rel2
+
+
 def test_fcg_truncated_solves_spd_systems_like_a_direct_solve():
     # the tangent at the reference configuration (linear elasticity) is positive definite
     mf, maskf, V = _two_level(amplitude=0.0)
