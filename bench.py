@@ -130,6 +130,42 @@ class Workload:
         return lambda: self.op.residual(self.u, store_state=True, out=self.r)
 
 
+def coarse_iteration(sizes, stream, k0=10, k1=210, reps=5):
+    """Time of one iteration of the assembled order-1 coarse Jacobi-PCG inside the
+    V-cycle, per precision, on the n^3 jittered box (Q4 -> Q2 -> Q1, (n+1)^3 coarse
+    nodes, x = 0 and x = 1 faces clamped, linearised at a 10 % stretch): the difference
+    of median V-cycle times with k1 and k0 fixed coarse iterations, over k1 - k0, for
+    both block layouts (a thread per row, a thread per node) and the default's choice."""
+    import torch
+    from paper_2204_01722_amd import inputs
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    out = {}
+    for n in sizes:
+        m = inputs.box_mesh(n, 4, jitter=0.05, seed=2204)
+        H = Hierarchy(m, [4, 2, 1], faces={"x0": (1, 1, 1), "x1": (1, 1, 1)})
+        u = torch.from_numpy(inputs.stretch_field(m, 1.1)).cuda()
+        H.fine.residual(u, store_state=True)
+        r = torch.from_numpy(inputs.random_vector(m.n_nodes, 5) * (1.0 - H.masks[0])).cuda()
+        rec = {"coarse_nodes": (n + 1) ** 3,
+               "default_layout": "nodes" if (n + 1) ** 3 >= 65536 else "rows"}
+        for prec in ("f64", "f32"):
+            for layout in ("rows", "nodes"):
+                ms = {}
+                for k in (k0, k1):
+                    mg = PMG(H.ops, precision=prec, cheb_degree=3, coarse_fixed_its=k, coarse_block_layout=layout)
+                    mg.setup(H.seeds(7))
+                    ms[k] = time_median(lambda: mg.vcycle(r), 10, 3, stream, reps=reps, prime_s=0.0)
+                    del mg
+                key = f"{prec}_{layout}_us_per_iteration"
+                rec[key] = (ms[k1] - ms[k0]) / (k1 - k0) * 1e3
+                print(f"[coarse] {(n + 1) ** 3} coarse nodes, {prec}, a thread per {layout[:-1]}: {rec[key]:.1f} us "
+                      f"per iteration", file=sys.stderr, flush=True)
+        out[f"{n}^3"] = rec
+        del H, u, r
+    return out
+
+
 def adjoint_bench(steps, warmup, stream):
     """The differentiation workload: Q3 on a 23^3 jittered box (1,029,000 DoF), per-element
     Lame parameters log-uniform on [0.5, 2]; times of the adjoint (VJP) kernel giving
@@ -415,6 +451,8 @@ def main():
     ap.add_argument("--profile-applies", action="store_true",
                     help="only run the stored Jacobian applies (Q4 34^3 and Q2 43^3, FP64 and FP32) --steps "
                          "times each, for a profiler")
+    ap.add_argument("--coarse-iteration", type=str, default=None, metavar="N1,N2,...",
+                    help="only time one coarse PCG iteration on the N^3 boxes (Q1 level of (N+1)^3 nodes)")
     ap.add_argument("--pmg-strain", type=float, default=0.10,
                     help="compressive strain of the multiscale block (0.10: solved on every mesh up to 80^3)")
     args = ap.parse_args()
@@ -428,6 +466,10 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.coarse_iteration:
+        sizes = [int(v) for v in args.coarse_iteration.split(",")]
+        print(json.dumps({"coarse_pcg_iteration": coarse_iteration(sizes, stream)}))
+        return
     if args.profile_applies:
         for n, p in ((34, 4), (43, 2)):
             wl = Workload(n, p)

@@ -261,6 +261,11 @@ typedef struct {
   int precision;        /* HPMG_F32: smoothing/transfer/coarse solve in FP32 */
   int coarse_element_matrices; /* 1: order-1 Galerkin coarsest level from element matrices,
                                   assembled into 3 x 3 node blocks for its Jacobi-PCG */
+  int coarse_block_layout; /* those blocks: -1 (default) by size, node-major from 65,536
+                              coarse nodes; 0: a node's rows contiguous, a thread per row
+                              (faster on small coarse levels); 1: each block entry
+                              contiguous over the nodes, a thread per node (faster once the
+                              blocks stream from HBM).  Same arithmetic either way */
 } hpmg_mg_params;
 
 void hpmg_mg_default_params(hpmg_mg_params *p);

@@ -36,7 +36,7 @@ class MGParams(C.Structure):
     _fields_ = [("cheb_degree", C.c_int), ("cheb_lo", C.c_double), ("cheb_hi", C.c_double),
                 ("lanczos_its", C.c_int), ("coarse_rtol", C.c_double), ("coarse_maxit", C.c_int),
                 ("coarse_fixed_its", C.c_int), ("precision", C.c_int),
-                ("coarse_element_matrices", C.c_int)]
+                ("coarse_element_matrices", C.c_int), ("coarse_block_layout", C.c_int)]
 
 
 class NewtonParams(C.Structure):
@@ -455,7 +455,7 @@ class PMG:
 
     def __init__(self, levels, precision="f64", cheb_degree=3, cheb_lo=0.1, cheb_hi=1.1,
                  lanczos_its=10, coarse_rtol=1e-3, coarse_maxit=10000, coarse_fixed_its=0,
-                 coarse_element_matrices=True):
+                 coarse_element_matrices=True, coarse_block_layout="auto"):
         self.levels = list(levels)
         prm = MGParams()
         lib().hpmg_mg_default_params(C.byref(prm))
@@ -463,6 +463,10 @@ class PMG:
         prm.lanczos_its, prm.coarse_rtol, prm.coarse_maxit = lanczos_its, coarse_rtol, coarse_maxit
         prm.coarse_fixed_its, prm.precision = coarse_fixed_its, _prec(precision)
         prm.coarse_element_matrices = int(bool(coarse_element_matrices))
+        layouts = {"auto": -1, "rows": 0, "nodes": 1}
+        if coarse_block_layout not in layouts:
+            raise ValueError(f"coarse_block_layout must be one of {sorted(layouts)}")
+        prm.coarse_block_layout = layouts[coarse_block_layout]
         self.params = prm
         arr = (C.c_void_p * len(self.levels))(*[op.h.value for op in self.levels])
         h = C.c_void_p()

@@ -137,16 +137,20 @@ hipError_t launch_fcg_update(int64_t n, double *sc, int it, const double *p, con
 hipError_t launch_fcg_dir(int64_t n, double *sc, int it, const double *z, double *p, hipStream_t s);
 // The iteration on an order-1 operator assembled into 3 x 3 blocks (sliced ELL, width W,
 // nn nodes): one launch replaces the element kernel, the fused assembly and dir2;
-// ell_pcg_blocks(nn) workgroups write pq_part.  nn = 0 runs only the stopping test of
-// the iteration before `it` (to close a batch).
-int ell_pcg_blocks(int64_t nn);
-hipError_t launch_ell_pcg_apply(int prec, int64_t nn, int W, const int32_t *cols, const void *vals, const void *z,
-                                const void *p_old, void *p_new, void *y, double *sc, const double *partial, int it,
-                                double rtol2, double *pq_part, hipStream_t s);
+// ell_pcg_blocks(nn, node_major) workgroups write pq_part.  nn = 0 runs only the
+// stopping test of the iteration before `it` (to close a batch).  node_major: blocks
+// held entry-major over the nodes and a thread per node (else a node's rows contiguous
+// and a thread per row), the same choice as the build's.
+// By default coarse levels of at least this many nodes are node-major.
+constexpr int64_t ELL_NODE_MAJOR_MIN = 65536;
+int ell_pcg_blocks(int64_t nn, bool node_major);
+hipError_t launch_ell_pcg_apply(int prec, bool node_major, int64_t nn, int W, const int32_t *cols,
+                                const void *vals, const void *z, const void *p_old, void *p_new, void *y, double *sc,
+                                const double *partial, int it, double rtol2, double *pq_part, hipStream_t s);
 // Assembles the order-1 element matrices of `op` (built in precision prec) into the
 // sliced-ELL blocks; constrained rows become identity rows, constrained columns zero.
-hipError_t launch_ell_build(const hpmg_op_s &op, int prec, int64_t W, const int32_t *cols, void *vals,
-                            hipStream_t s);
+hipError_t launch_ell_build(const hpmg_op_s &op, int prec, bool node_major, int64_t W, const int32_t *cols,
+                            void *vals, hipStream_t s);
 hipError_t launch_pcg_update2(int prec, int64_t n, double *sc, int parity, int nb_pq, const double *pq_partial,
                               const void *p, const void *q, void *x, void *r, const void *dinv, void *z,
                               double *partial, double *alpha_rec, hipStream_t s);

@@ -1246,13 +1246,15 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_apply(const uint32_t *__rest
 
 // The order-1 operator assembled into 3 x 3 node blocks, sliced ELL by slot (column
 // node cols[j][n], -1 - n past the row's end: a zero block; entry (i, k) at
-// vals[j][n][3 i + k]: the three rows of a node are contiguous).  One
+// vals[j][3 i + k][n] when node_major (each entry of a slot's blocks contiguous over the
+// nodes, for a thread per node), else at vals[j][n][3 i + k] (a node's three rows
+// contiguous, for a thread per row)).  One
 // thread per (slot, row node) sums the block over the elements that hold both nodes,
 // in the row node's incidence order (so the result is reproducible), in double, and
 // masks it like the matrix-free apply: constrained columns are zero, constrained rows
 // identity rows.
 template <typename T>
-__global__ __launch_bounds__(256) void k_ell_build(int64_t nn, int W, const int32_t *__restrict__ cols,
+__global__ __launch_bounds__(256) void k_ell_build(bool node_major, int64_t nn, int W, const int32_t *__restrict__ cols,
                                                    const int32_t *__restrict__ off, const int32_t *__restrict__ inc,
                                                    const uint32_t *__restrict__ emap, const T *__restrict__ K,
                                                    T *__restrict__ vals) {
@@ -1261,9 +1263,12 @@ __global__ __launch_bounds__(256) void k_ell_build(int64_t nn, int W, const int3
   const int j = (int)(t / nn);
   const int64_t n = t - (int64_t)j * nn;
   const int32_t c = cols[t];
+  // entry m of this block at blk[m * ms]
+  T *blk = node_major ? vals + (int64_t)j * 9 * nn + n : vals + t * 9;
+  const int64_t ms = node_major ? nn : 1;
   if (c < 0) {  // padding: a zero block
 #pragma unroll
-    for (int m = 0; m < 9; ++m) vals[t * 9 + m] = T(0);
+    for (int m = 0; m < 9; ++m) blk[m * ms] = T(0);
     return;
   }
   double a[9];
@@ -1295,7 +1300,7 @@ __global__ __launch_bounds__(256) void k_ell_build(int64_t nn, int W, const int3
     for (int kk = 0; kk < 3; ++kk) {
       double v = ((cbc >> kk) & 1u) ? 0.0 : a[i * 3 + kk];
       if ((rbc >> i) & 1u) v = (c == n && i == kk) ? 1.0 : 0.0;
-      vals[t * 9 + i * 3 + kk] = (T)v;
+      blk[(i * 3 + kk) * ms] = (T)v;
     }
 }
 
@@ -2045,15 +2050,16 @@ hipError_t launch_elmat_build(const hpmg_op_s &op, int prec, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ell_build(const hpmg_op_s &op, int prec, int64_t W, const int32_t *cols, void *vals,
+hipError_t launch_ell_build(const hpmg_op_s &op, int prec, bool node_major, int64_t W, const int32_t *cols,
+                            void *vals,
                             hipStream_t s) {
   if (op.P != 2 || !op.elmat || op.elmat_prec != prec) return hipErrorInvalidValue;
   const unsigned g = grid1d(W * op.N, 256);
   if (prec == HPMG_F64)
-    k_ell_build<double><<<g, 256, 0, s>>>(op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
+    k_ell_build<double><<<g, 256, 0, s>>>(node_major, op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
                                           (const double *)op.elmat, (double *)vals);
   else
-    k_ell_build<float><<<g, 256, 0, s>>>(op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
+    k_ell_build<float><<<g, 256, 0, s>>>(node_major, op.N, (int)W, cols, op.csr_off, op.csr_inc, op.emap,
                                          (const float *)op.elmat, (float *)vals);
   return hipGetLastError();
 }

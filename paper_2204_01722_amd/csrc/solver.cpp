@@ -56,6 +56,7 @@ struct hpmg_mg_s {
   int32_t *ell_cols = nullptr;
   void *ell_vals = nullptr;
   bool ell_ready = false;
+  bool ell_node_major = false;  // block layout and PCG body (coarse_block_layout)
   uint64_t ell_version = 0;  // fine state version the blocks were built from
   // counters since creation: V-cycles, coarse iterations, operator applies per level
   int64_t n_vcycles = 0, n_coarse_its = 0, n_setups = 0;
@@ -79,7 +80,8 @@ size_t mg_layout(hpmg_mg_s *mg, char *base) {
   mg->scal = reinterpret_cast<double *>(take(SC_N * sizeof(double)));
   int64_t nmax = 0;
   for (const Level &L : mg->lv) nmax = std::max<int64_t>(nmax, L.n / 3);
-  const int64_t nb_pq = std::max<int64_t>((nmax + 255) / 256, ell_pcg_blocks(mg->lv.back().n / 3));
+  const int64_t nb_pq =
+      std::max<int64_t>((nmax + 255) / 256, ell_pcg_blocks(mg->lv.back().n / 3, mg->ell_node_major));
   mg->pq_part = reinterpret_cast<double *>(take((size_t)(nb_pq + 1) * sizeof(double)));
   if (mg->ell_w > 0) {
     Level &C = mg->lv.back();
@@ -191,7 +193,7 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
   const hpmg_op_s *src = L.op->fine ? L.op->fine : L.op;  // holder of the level's linearisation
   const bool ell = !record && l + 1 == mg->lv.size() && mg->ell_ready && mg->ell_version == src->state_version;
   const int64_t nn = L.n / 3;
-  const int nb_pq = ell ? ell_pcg_blocks(nn) : (int)((nn + 255) / 256);
+  const int nb_pq = ell ? ell_pcg_blocks(nn, mg->ell_node_major) : (int)((nn + 255) / 256);
   int queued = 0, its = limit;
   int batch = fixed > 0 ? limit : std::max(check, predict), grow = check;
   while (queued < limit) {
@@ -201,7 +203,8 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
       if (ell) {
         // Direction of iteration `queued` in (L.d, L.p2)[parity], the previous one in the other.
         void *pn = parity ? L.p2 : L.d, *po = parity ? L.d : L.p2;
-        HPMG_HIP(launch_ell_pcg_apply(prec, nn, mg->ell_w, mg->ell_cols, mg->ell_vals, L.z, po, pn, L.t, sc,
+        HPMG_HIP(launch_ell_pcg_apply(prec, mg->ell_node_major, nn, mg->ell_w, mg->ell_cols, mg->ell_vals, L.z, po,
+                                      pn, L.t, sc,
                                       mg->red, queued, rtol2, mg->pq_part, s));
         HPMG_HIP(launch_pcg_update2(prec, L.n, sc, parity, nb_pq, mg->pq_part, pn, L.t, L.x, L.r, L.dinv, L.z,
                                     mg->red, nullptr, s));
@@ -217,7 +220,8 @@ int pcg_device(hpmg_mg_s *mg, Level &L, int prec, double rtol, int maxit, int fi
     }
     if (fixed > 0 && !record) break;  // no read: the count is the fixed one
     // the stopping test of the last queued iteration
-    if (ell) HPMG_HIP(launch_ell_pcg_apply(prec, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, sc,
+    if (ell) HPMG_HIP(launch_ell_pcg_apply(prec, mg->ell_node_major, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                           nullptr, sc,
                                            mg->red, queued, rtol2, nullptr, s));
     if ((st = read_scalars(mg, record ? SC_N : SC_RR0 + 1, s))) return st;
     if (mg->host[SC_STOP] != 0.0 || queued >= limit) {
@@ -394,7 +398,7 @@ int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
     Lc.op->elmat_prec = prec;
     Lc.op->elmat_version = src->state_version;
     if (mg->ell_w > 0) {
-      HPMG_HIP(launch_ell_build(*Lc.op, prec, mg->ell_w, mg->ell_cols, mg->ell_vals, s));
+      HPMG_HIP(launch_ell_build(*Lc.op, prec, mg->ell_node_major, mg->ell_w, mg->ell_cols, mg->ell_vals, s));
       mg->ell_ready = true;
       mg->ell_version = src->state_version;
     }
@@ -502,6 +506,7 @@ void hpmg_mg_default_params(hpmg_mg_params *p) {
   p->coarse_fixed_its = 0;
   p->precision = HPMG_F64;
   p->coarse_element_matrices = 1;
+  p->coarse_block_layout = -1;
 }
 
 int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *params, hpmg_mg *out) {
@@ -513,6 +518,8 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
   if (params->cheb_degree < 1 || !(params->cheb_lo > 0.0) || !(params->cheb_hi > params->cheb_lo) ||
       params->lanczos_its < 1 || params->lanczos_its > PCG_RECORD || params->coarse_maxit < 1)
     return fail(HPMG_ERR_ARG, "mg_create: bad smoother or coarse-solver parameters");
+  if (params->coarse_block_layout < -1 || params->coarse_block_layout > 1)
+    return fail(HPMG_ERR_ARG, "mg_create: coarse_block_layout must be -1, 0 or 1");
   const hpmg_op_s *f = levels[0];
   if (!f || f->fine) return fail(HPMG_ERR_ARG, "mg_create: levels[0] must be a fine operator");
   // Coarse levels are either all Galerkin (coarse operators of levels[0], sharing its
@@ -552,6 +559,8 @@ int hpmg_mg_create(const hpmg_op *levels, int n_levels, const hpmg_mg_params *pa
   // Galerkin order-1 coarsest level only: a rediscretised one on its own 2^3 Gauss points
   // is cheaper matrix-free than as assembled blocks (measured)
   if (!redisc && params->coarse_element_matrices && mg->lv.back().op->P == 2) {
+    const int64_t nn = mg->lv.back().n / 3;
+    mg->ell_node_major = params->coarse_block_layout < 0 ? nn >= ELL_NODE_MAJOR_MIN : params->coarse_block_layout == 1;
     const int st = build_ell_structure(mg);
     if (st) {
       delete mg;

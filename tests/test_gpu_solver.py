@@ -49,15 +49,16 @@ def _oracle_vcycle(m, H, u, coarse_fixed, degree=3):
     ((3, 2, 2), [3, 1], {"x0": (1, 1, 1)}),
     ((2, 1, 1), [2, 1], {"x0": (1, 1, 1)}),  # no node with 27 neighbours: general-width blocks
 ])
-def test_vcycle_matches_oracle(n, orders, faces):
+@pytest.mark.parametrize("layout", ["rows", "nodes"])
+def test_vcycle_matches_oracle(n, orders, faces, layout):
     from paper_2204_01722_amd.binding import PMG
-    print_case("vcycle", n=n, orders=orders)
+    print_case("vcycle", n=n, orders=orders, layout=layout)
     m, H, u = _build(n, orders, faces)
     V = _oracle_vcycle(m, H, u, coarse_fixed=8)
     fr = 1.0 - H.masks[0].reshape(-1)
     r = inputs.random_vector(m.n_nodes, 21).reshape(-1) * fr
     for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
-        pmg = PMG(H.ops, precision=prec, coarse_fixed_its=8)
+        pmg = PMG(H.ops, precision=prec, coarse_fixed_its=8, coarse_block_layout=layout)
         pmg.setup(H.seeds(7))
         for l in range(len(orders) - 1):
             lam, _ = pmg.info(l)
@@ -82,14 +83,53 @@ def test_vcycle_coarse_tolerance_matches_oracle(n, orders):
     rs = [inputs.random_vector(m.n_nodes, 23 + k).reshape(-1) * fr for k in range(3)]
     refs = [V(r) for r in rs]
     assert min(V.coarse_its) > 2
-    for elmat in (True, False):
-        pmg = PMG(H.ops, precision="f64", coarse_rtol=1e-3, coarse_element_matrices=elmat)
+    for elmat, layout in ((True, "rows"), (True, "nodes"), (False, "auto")):
+        pmg = PMG(H.ops, precision="f64", coarse_rtol=1e-3, coarse_element_matrices=elmat,
+                  coarse_block_layout=layout)
         pmg.setup(H.seeds(7))
         for r, ref, its_ref in zip(rs, refs, V.coarse_its):
             z = t2n(pmg.vcycle(_dev(r.reshape(-1, 3))))
             _, its = pmg.info(len(orders) - 1)
-            assert its == its_ref, (elmat, its, its_ref)
-            assert rel(z, ref) < 1e-10, (elmat, rel(z, ref))
+            assert its == its_ref, (elmat, layout, its, its_ref)
+            assert rel(z, ref) < 1e-10, (elmat, layout, rel(z, ref))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_coarse_block_layouts_agree_at_full_size(prec):
+    """Q2 -> Q1 on the 40^3 jittered box: the coarse level has 68,921 nodes, so the
+    default takes the node-major blocks (a thread per node).  Its V-cycle agrees with the
+    row-interleaved form's (pinned to the oracle on small meshes): with 8 fixed coarse
+    iterations to rounding; with the coarse PCG to 1e-3 (about a hundred iterations, over
+    which PCG amplifies the rounding differences of the two forms' p.Ap partial sums)
+    with the same iteration count in FP64 (at most one apart in FP32)."""
+    from paper_2204_01722_amd.binding import PMG
+    print_case("coarse_layouts_full", prec=prec)
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m, H, u = _build(40, [2, 1], faces, amplitude=0.02)
+    assert H.ops[1].n_nodes == 41 ** 3
+    r = _dev(inputs.random_vector(m.n_nodes, 29) * (1.0 - H.masks[0]))
+    for fixed in (8, 0):
+        out = {}
+        for layout in ("auto", "rows", "nodes"):
+            pmg = PMG(H.ops, precision=prec, coarse_rtol=1e-3, coarse_fixed_its=fixed, coarse_block_layout=layout)
+            pmg.setup(H.seeds(7))
+            z = t2n(pmg.vcycle(r))
+            out[layout] = (z, pmg.info(1)[1])
+            del pmg
+        assert np.array_equal(out["auto"][0], out["nodes"][0])  # the default is node-major here
+        d = rel(out["nodes"][0], out["rows"][0])
+        its = {k: v[1] for k, v in out.items()}
+        print(f"[coarse layouts] {prec} fixed={fixed}: coarse its {its}, rel diff {d:.2e}", flush=True)
+        if fixed:
+            assert its["rows"] == its["nodes"] == fixed
+            assert d < (1e-12 if prec == "f64" else 1e-5), d
+        elif prec == "f64":
+            assert its["rows"] == its["nodes"] > 2, its
+            assert d < 1e-6, d
+        else:
+            assert abs(its["rows"] - its["nodes"]) <= 1 and its["rows"] > 2, its
+    with pytest.raises(ValueError):
+        PMG(H.ops, coarse_block_layout="columns")
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
