@@ -119,8 +119,7 @@ bool supported_pq(int P, int Q);
 hipError_t launch_build_emap(const hpmg_op_s &op, hipStream_t s);
 hipError_t launch_mark_owners(const hpmg_op_s &op, hipStream_t s);
 // Stored-mode apply whose assembly also writes per-workgroup partials of du . y
-// (ceil(N / 256) of them, in pq); the atomic scatter mode is not supported.  With
-// `stop` set, every kernel of the apply returns at once while *stop != 0.
+// (ceil(N / 256) of them, in pq).  With `stop` set, every kernel of the apply returns at once while *stop != 0.
 hipError_t launch_jacobian_dot(const hpmg_op_s &op, int prec, const void *du, void *y, double *pq,
                                const double *stop, hipStream_t s);
 // Fused Jacobi-PCG iteration on the slots above; all kernels return at once while

@@ -1776,8 +1776,8 @@ hipError_t launch_qdata(const hpmg_op_s &op, const double *X, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-// Scatter flavour: HPMG_SCATTER=atomic selects hardware atomics into the output;
-// otherwise element records + the node-centric assembly pass (deterministic).
+// Residual: the element kernel writes element records, the node-centric assembly pass
+// sums them (deterministic).
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
 #define X(p, q)                                                                                  \
   if (op.P == p && op.Q == q) {                                                                  \
