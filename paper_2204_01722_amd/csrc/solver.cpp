@@ -460,10 +460,14 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
     HPMG_HIP(launch_jacobian(*fine, HPMG_F64, HPMG_STORED, nullptr, p, q, s));
     HPMG_HIP(launch_dot(HPMG_F64, n, p, q, mg->red, sc + FCG_PQ, s));
     HPMG_HIP(launch_fcg_update(n, sc, its, p, q, x, r, rn, mg->red, s));
+    double *zn = z;  // where M^-1 rn goes
     if (natural) {
-      // z = M^-1 rn and z.rn (the natural norm squared), z.r for the next direction
-      if ((st = vcycle(mg, rn, z, s))) return st;
-      HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));
+      // M^-1 rn and its dot with rn (the natural norm squared) and r, before the tests;
+      // into q's buffer (q is spent once x and rn are updated), so that z still holds
+      // M^-1 r for the breakdown path
+      zn = q;
+      if ((st = vcycle(mg, rn, zn, s))) return st;
+      HPMG_HIP(launch_dot_pair(HPMG_F64, n, zn, rn, r, mg->red, sc + FCG_ZRN, s));
     }
     if ((st = read_scalars(mg, FCG_RZ + 2, s))) return st;
     if (mg->host[FCG_BRK] != 0.0) {
@@ -482,8 +486,9 @@ int do_fcg(hpmg_op fine, hpmg_mg_s *mg, const double *b, double *x, double rtol,
       if ((st = vcycle(mg, rn, z, s))) return st;
       HPMG_HIP(launch_dot_pair(HPMG_F64, n, z, rn, r, mg->red, sc + FCG_ZRN, s));  // z.rn, z.r
     }
-    HPMG_HIP(launch_fcg_dir(n, sc, its - 1, z, p, s));
+    HPMG_HIP(launch_fcg_dir(n, sc, its - 1, zn, p, s));
     std::swap(r, rn);
+    if (natural) std::swap(z, q);
   }
   *its_out = its;
   *rel_out = rel;
