@@ -376,13 +376,16 @@ __device__ __forceinline__ int64_t xcd_tile() {
   return (int64_t)x * m + (x < r ? x : r) + j;
 }
 
-// Record traffic of FP64 order-4 operators (P = 5) goes through contiguous nontemporal
-// sweeps: the Jacobian kernel's records and the assembly's output (measured: 197 against
-// 217 us per Q4 apply on 34^3 elements); at the other orders and in FP32 the per-node
+// Record traffic of FP64 operators of order 4 and 2 (P = 5, 3) goes through contiguous
+// sweeps: the Jacobian kernel writes each tile's records from LDS as one run with plain
+// stores, so they stay in the last-level cache for the assembly that follows, and the
+// assembly writes its output from LDS in whole-line nontemporal sweeps (measured per Q4
+// apply on 34^3 elements: 187 us, against 198 us with nontemporal record stores and 217
+// us with per-node stores; Q2 on 43^3: 86.8 against 88.4 us).  In FP32 the per-node
 // stores were as fast or faster.
 template <typename T>
 __host__ __device__ constexpr bool sweep_records(int P) {
-  return std::is_same<T, double>::value && P == 5;
+  return std::is_same<T, double>::value && (P == 5 || P == 3);
 }
 
 __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
@@ -604,8 +607,8 @@ __device__ __forceinline__ void line_task(T *p, const T *__restrict__ M) {
 // + grad_X u [+ C^-1, lambda log J]); T = double.
 // MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
 // lambda log J are rebuilt from grad_X u and J; T = double.
-// SWEEP: the tile's element records leave LDS in contiguous nontemporal sweeps (each
-// store instruction covers whole cache lines) instead of three strided stores per node.
+// SWEEP: the tile's element records leave LDS in contiguous sweeps (each store
+// instruction covers whole cache lines) instead of three strided stores per node.
 template <typename T, int P, int Q, int MODE, bool SWEEP>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
@@ -665,9 +668,9 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   // task alike (element, component, line), only the line's direction changes, and each
   // thread has at most one such task: its line offsets are formed once here (the same
   // arithmetic in the same order as the generic stages; measured 3-4 % faster for
-  // order 4 in FP32 and order 2 in FP64, 1 % slower for the FP64 order-4 sweep form,
-  // which keeps the generic stages).
-  constexpr bool FI = (P == Q) && (ET * 3 * Q2 <= NT) && !SWEEP;
+  // order 4 in FP32 and order 2 in FP64, 1 % slower for order 4 in FP64, which keeps the
+  // generic stages).
+  constexpr bool FI = (P == Q) && (ET * 3 * Q2 <= NT) && !(std::is_same<T, double>::value && P == 5);
   const int e3 = tq / (3 * Q2), r3 = tq % (3 * Q2), c3 = r3 / Q2, ln3 = r3 % Q2;
   const bool a3 = tq < ET * 3 * Q2 && e3 < nel;
   T *const p3 = lds + (a3 ? e3 * ELS + c3 * Q3 : 0);
@@ -866,7 +869,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     for (int d = tq; d < nd; d += NT) {
       const int r = d / 3, c = d - 3 * r, te = r / P3, a = r - te * P3;
       const int an = (a % P) + Q * ((a / P) % P) + Q2 * (a / (P * P));
-      __builtin_nontemporal_store(lds[te * ELS + c * Q3 + an], o + d);
+      o[d] = lds[te * ELS + c * Q3 + an];
     }
   } else if (live && q < P3) {
     T *o = ev + ((int64_t)e * P3 + q) * 3;
