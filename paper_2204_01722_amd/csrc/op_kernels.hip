@@ -377,15 +377,22 @@ __device__ __forceinline__ int64_t xcd_tile() {
 }
 
 // Record traffic of FP64 operators of order 4 and 2 (P = 5, 3) goes through contiguous
-// sweeps: the Jacobian kernel writes each tile's records from LDS as one run with plain
-// stores, so they stay in the last-level cache for the assembly that follows, and the
-// assembly writes its output from LDS in whole-line nontemporal sweeps (measured per Q4
-// apply on 34^3 elements: 187 us, against 198 us with nontemporal record stores and 217
-// us with per-node stores; Q2 on 43^3: 86.8 against 88.4 us).  In FP32 the per-node
-// stores were as fast or faster.
+// sweeps: the Jacobian kernel writes each tile's records from LDS as one run, and the
+// assembly writes its output from LDS in whole-line nontemporal sweeps.  Records of up
+// to half the 256 MB last-level cache are stored with plain stores, so that they stay
+// there for the assembly that follows; larger ones stream out with nontemporal stores
+// (keep_records).  Measured per apply, plain against nontemporal record stores: Q4 on
+// 34^3 elements (118 MB of records) 188 against 201 us, Q2 on 43^3 (52 MB) 87.2 against
+// 92.5 us; Q4 on 68^3 (943 MB) 1750 against 1643 us, Q2 on 86^3 (412 MB) 766 against
+// 724 us; per-node stores: Q4 34^3 217 us, Q2 43^3 88.4 us, Q2 86^3 785 us.  In FP32
+// the per-node stores were as fast or faster.
 template <typename T>
 __host__ __device__ constexpr bool sweep_records(int P) {
   return std::is_same<T, double>::value && (P == 5 || P == 3);
+}
+template <typename T>
+bool keep_records(int64_t E, int P) {
+  return (double)E * P * P * P * 3 * sizeof(T) <= 128.0 * (1 << 20);
 }
 
 __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
@@ -607,9 +614,11 @@ __device__ __forceinline__ void line_task(T *p, const T *__restrict__ M) {
 // + grad_X u [+ C^-1, lambda log J]); T = double.
 // MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
 // lambda log J are rebuilt from grad_X u and J; T = double.
-// SWEEP: the tile's element records leave LDS in contiguous sweeps (each store
-// instruction covers whole cache lines) instead of three strided stores per node.
-template <typename T, int P, int Q, int MODE, bool SWEEP>
+// SWEEP 1 / 2: the tile's element records leave LDS in contiguous sweeps (each store
+// instruction covers whole cache lines) with plain (1) or nontemporal (2) stores, instead
+// of three strided stores per node (0).  The two sweep kinds are separate instances: a
+// run-time choice lets the compiler merge both stores into a plain one.
+template <typename T, int P, int Q, int MODE, int SWEEP>
 __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const double *__restrict__ geo, const double *__restrict__ sinit,
@@ -862,14 +871,17 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     line_stage<T, Q, 0, Q, P, true, P, P, ET, ELS>(lds, tB, tq, NT, nel);
   }
   __syncthreads();
-  if constexpr (SWEEP) {
+  if constexpr (SWEEP > 0) {
     // records [e][a][c] of the tile's elements are one contiguous run of nel P^3 3 values
     T *o = ev + tile * (int64_t)(ET * P3 * 3);
     const int nd = nel * P3 * 3;
     for (int d = tq; d < nd; d += NT) {
       const int r = d / 3, c = d - 3 * r, te = r / P3, a = r - te * P3;
       const int an = (a % P) + Q * ((a / P) % P) + Q2 * (a / (P * P));
-      o[d] = lds[te * ELS + c * Q3 + an];
+      if constexpr (SWEEP == 1)
+        o[d] = lds[te * ELS + c * Q3 + an];
+      else
+        __builtin_nontemporal_store(lds[te * ELS + c * Q3 + an], o + d);
     }
   } else if (live && q < P3) {
     T *o = ev + ((int64_t)e * P3 + q) * 3;
@@ -877,6 +889,19 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     o[0] = y0;
     o[1] = y1;
     o[2] = y2;
+  }
+}
+
+// Launches k_jacobian_lines with the record-store form for its order, precision and size.
+template <typename T, int P, int Q, int MODE, typename... A>
+void lines_launch(unsigned tiles, hipStream_t s, bool keep, A... a) {
+  if constexpr (sweep_records<T>(P)) {
+    if (keep)
+      k_jacobian_lines<T, P, Q, MODE, 1><<<tiles, QT<Q>::NT, 0, s>>>(a...);
+    else
+      k_jacobian_lines<T, P, Q, MODE, 2><<<tiles, QT<Q>::NT, 0, s>>>(a...);
+  } else {
+    k_jacobian_lines<T, P, Q, MODE, 0><<<tiles, QT<Q>::NT, 0, s>>>(a...);
   }
 }
 
@@ -1859,24 +1884,25 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
                               T *ev, const double *stop, hipStream_t s) {
   const T *state = std::is_same<T, double>::value ? (const T *)f.state64 : (const T *)f.state32;
   const T *tab = std::is_same<T, double>::value ? (const T *)op.tab64 : (const T *)op.tab32;
-  constexpr bool SW = sweep_records<T>(P);
+  const bool keep = keep_records<T>(op.E, P);
+  const unsigned g = (unsigned)op.tiles;
   if constexpr (std::is_same<T, double>::value) {
     if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
       if (mode == HPMG_INITIAL_NATIVE)
-        k_jacobian_lines<T, P, Q, 1, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
+        lines_launch<T, P, Q, 1>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
+                                 op.lam_e, ev, op.E, nullptr);
       else if (mode == HPMG_INITIAL_TUNED)
-        k_jacobian_lines<T, P, Q, 2, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
+        lines_launch<T, P, Q, 2>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
+                                 op.lam_e, ev, op.E, nullptr);
       else
-        k_jacobian_lines<T, P, Q, 3, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-            op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, nullptr);
+        lines_launch<T, P, Q, 3>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
+                                 op.lam_e, ev, op.E, nullptr);
       return hipGetLastError();
     }
   }
   if (mode == HPMG_STORED) {
-    k_jacobian_lines<T, P, Q, 0, SW><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(
-        op.emap, du, state, nullptr, nullptr, tab, f.mu, f.lam, f.mu_e, f.lam_e, ev, op.E, stop);
+    lines_launch<T, P, Q, 0>(g, s, keep, op.emap, du, state, nullptr, nullptr, tab, f.mu, f.lam, f.mu_e, f.lam_e,
+                             ev, op.E, stop);
   } else {
     k_jacobian_recompute<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, u, du, op.geo, tab, op.mu,
                                                                            op.lam, op.mu_e, op.lam_e, ev, op.E);
