@@ -379,20 +379,22 @@ __device__ __forceinline__ int64_t xcd_tile() {
 // Record traffic of FP64 operators of order 4 and 2 (P = 5, 3) goes through contiguous
 // sweeps: the Jacobian kernel writes each tile's records from LDS as one run, and the
 // assembly writes its output from LDS in whole-line nontemporal sweeps.  Records of up
-// to half the 256 MB last-level cache are stored with plain stores, so that they stay
-// there for the assembly that follows; larger ones stream out with nontemporal stores
-// (keep_records).  Measured per apply, plain against nontemporal record stores: Q4 on
-// 34^3 elements (118 MB of records) 188 against 201 us, Q2 on 43^3 (52 MB) 87.2 against
-// 92.5 us; Q4 on 68^3 (943 MB) 1750 against 1643 us, Q2 on 86^3 (412 MB) 766 against
-// 724 us; per-node stores: Q4 34^3 217 us, Q2 43^3 88.4 us, Q2 86^3 785 us.  In FP32
-// the per-node stores were as fast or faster.
+// to 160 MiB (keep_records) are stored with plain stores, so that they stay in the
+// 256 MB last-level cache for the assembly that follows; larger ones stream out with
+// nontemporal stores.  Measured per apply, plain against nontemporal record stores:
+// Q2 on 43^3 elements (52 MB of records) 87.2 against 92.5 us, Q4 on 34^3 (118 MB) 188
+// against 201 us, Q2 on 60^3 (140 MB) 220 against 235 us; Q4 on 40^3 (192 MB) 354
+// against 331 us, Q4 on 46^3 (292 MB) 549 against 515 us, Q2 on 86^3 (412 MB) 766
+// against 724 us, Q4 on 68^3 (943 MB) 1750 against 1643 us; per-node stores: Q4 34^3
+// 217 us, Q2 43^3 88.4 us, Q2 86^3 785 us.  In FP32 the per-node stores were as fast or
+// faster.
 template <typename T>
 __host__ __device__ constexpr bool sweep_records(int P) {
   return std::is_same<T, double>::value && (P == 5 || P == 3);
 }
 template <typename T>
 bool keep_records(int64_t E, int P) {
-  return (double)E * P * P * P * 3 * sizeof(T) <= 128.0 * (1 << 20);
+  return (double)E * P * P * P * 3 * sizeof(T) <= 160.0 * (1 << 20);
 }
 
 __device__ __forceinline__ double mat_mu(double mu0, const double *mu_e, int64_t e) {
