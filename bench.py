@@ -5,7 +5,7 @@ Workload (the operator-at-scale configuration): jittered unit-cube box meshes wi
 smooth displacement of maximum stretch 1.3, E = 1, nu = 0.3,
   * Q4 (P = 5 nodes, 5^3 Gauss points) on 34^3 elements: 7,714,059 DoF  (headline)
   * Q2 (P = 3, 3^3 points) on 43^3 elements: 1,975,509 DoF.
-A timed "step" is one FP64 Jacobian apply y = J(u) du from the stored 17-scalar
+A timed "step" is one FP64 Jacobian apply y = J(u) du from the stored 16-scalar
 linearisation (gather, sum-factorised gradient, pointwise tangent, transpose, scatter),
 inputs resident in HBM.  The JSON line also carries Q2 / FP32 / recompute variants,
 the residual, the roofline of the apply kernel, an FP64-vs-mixed p-multigrid solve,
@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 
 
-def algorithmic_bytes(E, P, Q, N, word, nstate=17, nvec=2):
+def algorithmic_bytes(E, P, Q, N, word, nstate=16, nvec=2):
     """Bytes each apply must move once: the per-point linearisation, the input and
     output L-vectors, and the int32 element-to-node map."""
     return E * Q ** 3 * nstate * word + nvec * 3 * N * word + 4 * E * P ** 3
@@ -578,7 +578,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "Q4 (P=5 GLL nodes, 5^3 Gauss points) on a 34^3 jittered unit box, "
-                               "7,714,059 DoF, stored 17-scalar FP64 Jacobian apply, max stretch 1.3, "
+                               "7,714,059 DoF, stored 16-scalar FP64 Jacobian apply, max stretch 1.3, "
                                "E=1, nu=0.3", "global_batch": 1, "seq_len": 0, "parallelism": "none"},
         "roofline": {"bound": "hbm", "kernel": "k_jacobian_lines<double,5,5> + k_assemble<double> (one apply)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

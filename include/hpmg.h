@@ -49,7 +49,7 @@ typedef enum {
 
 typedef enum { HPMG_F64 = 0, HPMG_F32 = 1 } hpmg_precision;
 typedef enum {
-  HPMG_STORED = 0,         /* the 17-scalar current-configuration state (Section III-B) */
+  HPMG_STORED = 0,         /* the current-configuration state (Section III-B), 16 scalars */
   HPMG_RECOMPUTE = 1,      /* rebuilt from u and the geometric factors */
   HPMG_INITIAL_NATIVE = 2, /* initial configuration, 19 scalars: W, grad_X xi; grad_X u */
   HPMG_INITIAL_TUNED = 3,  /* initial configuration, 26 scalars: + C^-1, lambda log J */
@@ -136,9 +136,12 @@ int hpmg_qdata_export(hpmg_op op, double *out, void *stream);
 
 /* a2-a7: residual F(u) of eq. residual-discrete-ref with f_1 = Kirchhoff stress
  * (eq. Kirchhoff-stress) pulled back to reference coordinates.  u, r: device double
- * [n_nodes][3].  With store_state != 0 it also stores the 17-scalar linearisation
- * (dxi/dx, tau, lambda log J, W; Section III-B, Table different-storage) used by
- * stored-mode Jacobian applies of this operator and its coarse operators. */
+ * [n_nodes][3].  With store_state != 0 it also stores the linearisation of the
+ * current-configuration form (Section III-B, Table different-storage: dxi/dx, tau,
+ * lambda log J and the weight W, 17 scalars) as 16: sqrt(W) dxi/dx, tau, lambda log J
+ * (every use is W times a form bilinear in dxi/dx), used by stored-mode Jacobian
+ * applies, the diagonal, the element matrices and the adjoint of this operator and its
+ * coarse operators. */
 int hpmg_residual(hpmg_op op, const double *u, double *r, int store_state, void *stream);
 
 /* a5/a5': Jacobian action y = J(u) du (eqs. Jacobian, dtau, Jacobian-discrete-ref).

@@ -25,7 +25,10 @@ constexpr int tile_threads(int Q) {
 }
 
 constexpr int NGEO = 10;    // W, dxi_k/dX_J (row-major)
-constexpr int NSTATE = 17;  // dxi_k/dx_j (9), tau (xx yy zz yz xz xy), lambda log J, W
+// Stored linearisation per point: sqrt(W) dxi_k/dx_j (9), tau (xx yy zz yz xz xy),
+// lambda log J.  Every use is W times a form bilinear in dxi/dx, so the weight rides in
+// the scaled dxi/dx and is not stored (16 scalars instead of 17).
+constexpr int NSTATE = 16;
 constexpr int NINIT = 26;   // grad_X u (9), C^-1 (6), lambda log J (1), dxi/dx (9), J - 1 (1)
 
 // Reference tables, in the operator's precision, at fixed offsets (max 8 x 8 each).

@@ -475,7 +475,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// a2-a7: residual (FP64), optionally storing the 17-scalar linearisation.
+// a2-a7: residual (FP64), optionally storing the 16-scalar linearisation
+// (sqrt(W) dxi/dx, tau, lambda log J).
 // ------------------------------------------------------------------------------------
 template <int P, int Q>
 __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
@@ -525,15 +526,16 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_residual(
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
     if (state) {
+      // sqrt(W) dxi/dx, tau, lambda log J (the weight rides in the scaled dxi/dx)
       double *s = state + tile * NSTATE * NQ + tq;
+      const double sw = sqrt((double)W);
 #pragma unroll
       for (int kk = 0; kk < 3; ++kk)
 #pragma unroll
-        for (int j = 0; j < 3; ++j) s[(kk * 3 + j) * NQ] = k.A[kk][j];
+        for (int j = 0; j < 3; ++j) s[(kk * 3 + j) * NQ] = sw * k.A[kk][j];
 #pragma unroll
       for (int m = 0; m < 6; ++m) s[(9 + m) * NQ] = k.tau[m];
       s[15 * NQ] = k.c;
-      s[16 * NQ] = W;
     }
   }
   __syncthreads();
@@ -611,7 +613,8 @@ __device__ __forceinline__ void line_task(T *p, const T *__restrict__ M) {
   for (int i = 0; i < NO; ++i) p[i * ST] = y[i];
 }
 
-// MODE 0: the 17-scalar current-configuration state (T = double or float).
+// MODE 0: the 16-scalar current-configuration state (sqrt(W) dxi/dx, tau, lambda log J;
+// T = double or float).
 // MODE 1 / 2: the initial-configuration forms, 19 / 26 scalars (geometry W, grad_X xi
 // + grad_X u [+ C^-1, lambda log J]); T = double.
 // MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
@@ -768,7 +771,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
         for (int j = 0; j < 3; ++j) A[k][j] = sv[k * 3 + j];
 #pragma unroll
       for (int m = 0; m < 6; ++m) tau[m] = sv[9 + m];
-      const T c = sv[15], W = sv[16];
+      const T c = sv[15], W = T(1);  // the weight is in the scaled dxi/dx
       const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
       jacobian_qf(Gq, A, tau, c, W, mu, lam, f);
     } else if constexpr (MODE == 3) {
@@ -1129,6 +1132,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
 // ------------------------------------------------------------------------------------
 // a8: diagonal.  Per quadrature point and component i, the 3x3 block
 //   K^(i)_kl = W [ (A tau A^T)_kl + (mu - c)(A A^T)_kl + (lambda + mu - c) A_ki A_li ]
+// (from the stored sqrt(W) A the weight comes out of the products itself)
 // (the Jacobian map with G = e_i grad(phi)^T); the node value is
 //   sum_q sum_kl K^(i)_kl dphi/dxi_k dphi/dxi_l,
 // a tensor product of the 1D elementwise tables B*B, B*G, G*G, contracted in three
@@ -1161,7 +1165,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_diagonal(
       for (int j = 0; j < 3; ++j) A[k][j] = s[(k * 3 + j) * NQ];
 #pragma unroll
     for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
-    const T c = s[15 * NQ], W = s[16 * NQ];
+    const T c = s[15 * NQ], W = T(1);  // the weight is in the scaled dxi/dx
     const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
     T AT[3][3];  // (A tau)
     for (int k = 0; k < 3; ++k)
@@ -1255,7 +1259,7 @@ __global__ __launch_bounds__(ELB * 24) void k_elmat_build(const T *__restrict__ 
       for (int jj = 0; jj < 3; ++jj) A[a][jj] = s[(a * 3 + jj) * NQ + q];
 #pragma unroll
     for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ + q];
-    const T c = s[15 * NQ + q], W = s[16 * NQ + q];
+    const T c = s[15 * NQ + q], W = T(1);  // the weight is in the scaled dxi/dx
     // reference gradient of basis b at q
     const T Bx = sB[q1 * 2 + b1], By = sB[q2 * 2 + b2], Bz = sB[q3 * 2 + b3];
     const T Gx = sG[q1 * 2 + b1], Gy = sG[q2 * 2 + b2], Gz = sG[q3 * 2 + b3];
@@ -1575,7 +1579,13 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_vjp(
 #pragma unroll
       for (int m = 0; m < 6; ++m) tau[m] = s[(9 + m) * NQ];
       c = s[15 * NQ];
-      W = s[16 * NQ];
+      // the stored dxi/dx carries sqrt(W): unscale it with the geometry's weight
+      W = (T)geo[tile * NGEO * NQ + tq];
+      const T rsw = T(1) / (T)sqrt((double)W);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) A[k][j] *= rsw;
       // tau = 2 mu e + c I and c = lambda log J
 #pragma unroll
       for (int m = 0; m < 6; ++m) twoe[m] = (tau[m] - (m < 3 ? c : T(0))) / mu;
