@@ -475,79 +475,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict_
 }
 
 // ------------------------------------------------------------------------------------
-// a2-a7: residual (FP64), optionally storing the 16-scalar linearisation
-// (sqrt(W) dxi/dx, tau, lambda log J).
-// ------------------------------------------------------------------------------------
-template <int P, int Q>
-__global__ __launch_bounds__(QT<Q>::NT) void k_residual(
-    const uint32_t *__restrict__ emap, const double *__restrict__ u, const double *__restrict__ geo,
-    const double *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, double *__restrict__ state, unsigned *__restrict__ flags,
-    double *__restrict__ ev, int64_t E) {
-  using T = double;
-  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
-  constexpr int S0 = 9 * Q3, S1 = 3 * Q3;
-  __shared__ T sB[Q * P], sD[Q * Q];
-  __shared__ T lds[ET * (S0 + S1)];
-  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t tile = xcd_tile();
-  const int64_t e = tile * ET + el;
-  const bool live = tq < NQ && e < E;
-  uint32_t w = 0;
-  if (live && q < P3) w = emap[e * P3 + q];
-  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
-  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
-  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  if (live && q < P3) gather_node(u, w, false, a, q, P3);
-  T gv[NGEO];
-  if (live) {
-    const double *g = geo + tile * NGEO * NQ + tq;
-#pragma unroll
-    for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
-  }
-  __syncthreads();
-  interp<T, P, Q, 3>(a, b, sB, q, live);
-  if (live) {
-    T G[3][3], D[3][3];
-    grad_q<T, Q, 3>(b, sD, q, G);
-    const T W = gv[0];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int J = 0; J < 3; ++J) D[k][J] = gv[1 + k * 3 + J];
-    const T mu = mat_mu(mu0, mu_e, e), lam = mat_mu(lam0, lam_e, e);
-    Kin<T> k;
-    kinematics(G, D, mu, lam, k);
-    if (!(k.Jm1 > -1.0)) atomicOr(flags, k.Jm1 == k.Jm1 ? HPMG_FLAG_NONPOSITIVE_J : HPMG_FLAG_NONFINITE);
-    T f[3][3];
-    residual_qf(k, W, f);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
-    if (state) {
-      // sqrt(W) dxi/dx, tau, lambda log J (the weight rides in the scaled dxi/dx)
-      double *s = state + tile * NSTATE * NQ + tq;
-      const double sw = sqrt((double)W);
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) s[(kk * 3 + j) * NQ] = sw * k.A[kk][j];
-#pragma unroll
-      for (int m = 0; m < 6; ++m) s[(9 + m) * NQ] = k.tau[m];
-      s[15 * NQ] = k.c;
-    }
-  }
-  __syncthreads();
-  grad_t_q<T, Q>(a, sD, q, b, live);
-  __syncthreads();
-  interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) store_record(ev, e, a, q, P3);
-}
-
-// ------------------------------------------------------------------------------------
-// a5: Jacobian action from the stored linearisation (FP64 or FP32), with
-// register-blocked 1D contractions.
+// a4-a7: residual (FP64, MODE 4 below) and a5: Jacobian action from the stored
+// linearisation (FP64 or FP32), with register-blocked 1D contractions.
 //
 // With one thread per point, each 1D contraction would cost a thread one LDS read per
 // input of every output.  Here every contraction stage is run by "line tasks": a task owns one line of points along the contraction direction (for one
@@ -619,6 +548,9 @@ __device__ __forceinline__ void line_task(T *p, const T *__restrict__ M) {
 // + grad_X u [+ C^-1, lambda log J]); T = double.
 // MODE 3: the 20-scalar current-configuration form (dxi/dx, J, grad_X u, W): tau and
 // lambda log J are rebuilt from grad_X u and J; T = double.
+// MODE 4: the residual (du is u, unmasked; T = double): kinematics and the Kirchhoff
+// flux from the geometry (W, dxi/dX), the 16-scalar state written to state_out when it
+// is given, non-positive or non-finite J raised in flags.
 // SWEEP 1 / 2: the tile's element records leave LDS in contiguous sweeps (each store
 // instruction covers whole cache lines) with plain (1) or nontemporal (2) stores, instead
 // of three strided stores per node (0).  The two sweep kinds are separate instances: a
@@ -628,8 +560,10 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t *__restrict__ emap, const T *__restrict__ du, const T *__restrict__ state,
     const double *__restrict__ geo, const double *__restrict__ sinit,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
-    const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E, const double *__restrict__ stop) {
+    const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E, const double *__restrict__ stop,
+    double *__restrict__ state_out, unsigned *__restrict__ flags) {
   constexpr int NH = MODE == 2 ? 16 : MODE == 3 ? 19 : 9;
+  static_assert(MODE != 4 || std::is_same<T, double>::value, "the residual form is FP64");
   if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
   constexpr int Q2 = Q * Q, Q3 = Q2 * Q, P3 = P * P * P, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT;
   // Per element: v [3][Q^3] (du, then its values at the points, then the z-derivative
@@ -650,9 +584,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const uint32_t w = emap[e * P3 + q];
     const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
     const T x0 = src[0], x1 = src[1], x2 = src[2];
-    v[qn] = ((w >> EMAP_BC_SHIFT) & 1u) ? T(0) : x0;
-    v[Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 1)) & 1u) ? T(0) : x1;
-    v[2 * Q3 + qn] = ((w >> (EMAP_BC_SHIFT + 2)) & 1u) ? T(0) : x2;
+    // the residual takes u whole; the Jacobian forms zero the constrained components
+    const uint32_t bc = MODE == 4 ? 0u : (w >> EMAP_BC_SHIFT);
+    v[qn] = (bc & 1u) ? T(0) : x0;
+    v[Q3 + qn] = ((bc >> 1) & 1u) ? T(0) : x1;
+    v[2 * Q3 + qn] = ((bc >> 2) & 1u) ? T(0) : x2;
   }
   T sv[MODE == 0 ? NSTATE : 1];
   double gv[MODE == 0 ? 1 : MODE == 3 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
@@ -668,6 +604,10 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
       for (int f = 0; f < 9; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
 #pragma unroll
       for (int f = 0; f < 10; ++f) hv[9 + f] = __builtin_nontemporal_load(h + (16 + f) * NQ);
+    } else if constexpr (MODE == 4) {
+      const double *g = geo + tile * NGEO * NQ + tq;
+#pragma unroll
+      for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
     } else {
       const double *g = geo + tile * NGEO * NQ + tq;
 #pragma unroll
@@ -790,6 +730,28 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
           tau[sym_index(i, j)] = mu * (hv[i * 3 + j] + hv[j * 3 + i] + hh) + (i == j ? c : 0.0);
         }
       jacobian_qf(Gq, A, tau, c, gv[0], mu, lam, f);
+    } else if constexpr (MODE == 4) {
+      double D[3][3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int J = 0; J < 3; ++J) D[k][J] = gv[1 + k * 3 + J];
+      Kin<double> k;
+      kinematics(Gq, D, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), k);
+      if (!(k.Jm1 > -1.0)) atomicOr(flags, k.Jm1 == k.Jm1 ? HPMG_FLAG_NONPOSITIVE_J : HPMG_FLAG_NONFINITE);
+      residual_qf(k, gv[0], f);
+      if (state_out) {
+        // sqrt(W) dxi/dx, tau, lambda log J (the weight rides in the scaled dxi/dx)
+        double *so = state_out + tile * NSTATE * NQ + tq;
+        const double sw = sqrt(gv[0]);
+#pragma unroll
+        for (int kk = 0; kk < 3; ++kk)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) so[(kk * 3 + j) * NQ] = sw * k.A[kk][j];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) so[(9 + m) * NQ] = k.tau[m];
+        so[15 * NQ] = k.c;
+      }
     } else {
       jacobian_qf_initial<MODE == 2>(Gq, gv, hv, mat_mu(mu0, mu_e, e), mat_mu(lam0, lam_e, e), f);
     }
@@ -1878,10 +1840,10 @@ hipError_t launch_qdata(const hpmg_op_s &op, const double *X, hipStream_t s) {
 hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool store, hipStream_t s) {
 #define X(p, q)                                                                                  \
   if (op.P == p && op.Q == q) {                                                                  \
-    k_residual<p, q><<<(unsigned)op.tiles, QT<q>::NT, 0, s>>>(op.emap, u, op.geo, op.tab64, op.mu, op.lam, \
-                                                              op.mu_e, op.lam_e,                 \
-                                                              store ? op.state64 : nullptr, op.flags, op.evec, \
-                                                              op.E);                             \
+    lines_launch<double, p, q, 4>((unsigned)op.tiles, s, keep_records<double>(op.E, p), op.emap, u,            \
+                                  (const double *)nullptr, op.geo, (const double *)nullptr, op.tab64, op.mu,      \
+                                  op.lam, op.mu_e, op.lam_e, (double *)op.evec, op.E, (const double *)nullptr,    \
+                                  store ? op.state64 : nullptr, op.flags);                                        \
     hipError_t e = hipGetLastError();                                                            \
     if (e != hipSuccess) return e;                                                               \
     return assemble<double>(op, nullptr, r, s);                                                  \
@@ -1902,19 +1864,19 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
     if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
       if (mode == HPMG_INITIAL_NATIVE)
         lines_launch<T, P, Q, 1>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
       else if (mode == HPMG_INITIAL_TUNED)
         lines_launch<T, P, Q, 2>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
       else
         lines_launch<T, P, Q, 3>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
       return hipGetLastError();
     }
   }
   if (mode == HPMG_STORED) {
     lines_launch<T, P, Q, 0>(g, s, keep, op.emap, du, state, nullptr, nullptr, tab, f.mu, f.lam, f.mu_e, f.lam_e,
-                             ev, op.E, stop);
+                             ev, op.E, stop, nullptr, nullptr);
   } else {
     k_jacobian_recompute<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, u, du, op.geo, tab, op.mu,
                                                                            op.lam, op.mu_e, op.lam_e, ev, op.E);
