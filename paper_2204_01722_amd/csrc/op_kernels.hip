@@ -551,6 +551,9 @@ __device__ __forceinline__ void line_task(T *p, const T *__restrict__ M) {
 // MODE 4: the residual (du is u, unmasked; T = double): kinematics and the Kirchhoff
 // flux from the geometry (W, dxi/dX), the 16-scalar state written to state_out when it
 // is given, non-positive or non-finite J raised in flags.
+// MODE 5: the Jacobian with the linearisation recomputed at u (T = double or float; u
+// is converted to T): the kinematics of u from the geometry at every point, then the
+// action on du as in MODE 0.
 // SWEEP 1 / 2: the tile's element records leave LDS in contiguous sweeps (each store
 // instruction covers whole cache lines) with plain (1) or nontemporal (2) stores, instead
 // of three strided stores per node (0).  The two sweep kinds are separate instances: a
@@ -561,7 +564,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     const double *__restrict__ geo, const double *__restrict__ sinit,
     const T *__restrict__ tab, double mu0, double lam0, const double *__restrict__ mu_e,
     const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E, const double *__restrict__ stop,
-    double *__restrict__ state_out, unsigned *__restrict__ flags) {
+    double *__restrict__ state_out, unsigned *__restrict__ flags, const double *__restrict__ u) {
   constexpr int NH = MODE == 2 ? 16 : MODE == 3 ? 19 : 9;
   static_assert(MODE != 4 || std::is_same<T, double>::value, "the residual form is FP64");
   if (stop && *stop != 0.0) return;  // a stopped PCG (uniform over the grid)
@@ -580,19 +583,42 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   T *v = lds + (live ? el : 0) * ELS, *G = v + 3 * Q3;
   // Frame index of node q (q < P^3).
   const int qn = (q % P) + Q * ((q / P) % P) + Q2 * (q / (P * P));
+  T sv[MODE == 0 ? NSTATE : 1];
+  double gv[MODE == 0 ? 1 : MODE == 3 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
+  // FI: with P == Q every stage of 3 Q^2 line tasks per element decomposes a thread's
+  // task alike (element, component, line), only the line's direction changes, and each
+  // thread has at most one such task: its line offsets are formed once here (the same
+  // arithmetic in the same order as the generic stages; measured 3-4 % faster for
+  // order 4 in FP32 and order 2 in FP64, 1 % slower for order 4 in FP64, which keeps the
+  // generic stages).
+  constexpr bool FI = (P == Q) && (ET * 3 * Q2 <= NT) && !(std::is_same<T, double>::value && P == 5);
+  const int e3 = tq / (3 * Q2), r3 = tq % (3 * Q2), c3 = r3 / Q2, ln3 = r3 % Q2;
+  const bool a3 = tq < ET * 3 * Q2 && e3 < nel;
+  T *const p3 = lds + (a3 ? e3 * ELS + c3 * Q3 : 0);
+  const int lb0 = line_base<Q, 0, Q>(ln3), lb1 = line_base<Q, 1, Q>(ln3), lb2 = line_base<Q, 2, Q>(ln3);
+  // MODE 5 runs the forward stages twice: on u first (pass 0), keeping the kinematics of
+  // each point in registers, then, like every form, on du (pass 1).
+  T kA[3][3], ktau[6], kc = T(0);
+#pragma unroll 1
+  for (int pass = MODE == 5 ? 0 : 1; pass < 2; ++pass) {
   if (live && q < P3) {
     const uint32_t w = emap[e * P3 + q];
-    const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
-    const T x0 = src[0], x1 = src[1], x2 = src[2];
-    // the residual takes u whole; the Jacobian forms zero the constrained components
-    const uint32_t bc = MODE == 4 ? 0u : (w >> EMAP_BC_SHIFT);
+    T x0, x1, x2;
+    if (MODE == 5 && pass == 0) {
+      const double *src = u + (int64_t)(w & EMAP_ID_MASK) * 3;
+      x0 = (T)src[0], x1 = (T)src[1], x2 = (T)src[2];
+    } else {
+      const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
+      x0 = src[0], x1 = src[1], x2 = src[2];
+    }
+    // u is taken whole (the residual, the recompute form's first pass); du has its
+    // constrained components zeroed
+    const uint32_t bc = (MODE == 4 || pass == 0) ? 0u : (w >> EMAP_BC_SHIFT);
     v[qn] = (bc & 1u) ? T(0) : x0;
     v[Q3 + qn] = ((bc >> 1) & 1u) ? T(0) : x1;
     v[2 * Q3 + qn] = ((bc >> 2) & 1u) ? T(0) : x2;
   }
-  T sv[MODE == 0 ? NSTATE : 1];
-  double gv[MODE == 0 ? 1 : MODE == 3 ? 1 : NGEO], hv[MODE == 0 ? 1 : NH];
-  if (live) {
+  if (live && (MODE != 5 || pass == 0)) {
     if constexpr (MODE == 0) {
       const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
@@ -604,7 +630,7 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
       for (int f = 0; f < 9; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
 #pragma unroll
       for (int f = 0; f < 10; ++f) hv[9 + f] = __builtin_nontemporal_load(h + (16 + f) * NQ);
-    } else if constexpr (MODE == 4) {
+    } else if constexpr (MODE == 4 || MODE == 5) {
       const double *g = geo + tile * NGEO * NQ + tq;
 #pragma unroll
       for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
@@ -618,17 +644,6 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     }
   }
   __syncthreads();
-  // FI: with P == Q every stage of 3 Q^2 line tasks per element decomposes a thread's
-  // task alike (element, component, line), only the line's direction changes, and each
-  // thread has at most one such task: its line offsets are formed once here (the same
-  // arithmetic in the same order as the generic stages; measured 3-4 % faster for
-  // order 4 in FP32 and order 2 in FP64, 1 % slower for order 4 in FP64, which keeps the
-  // generic stages).
-  constexpr bool FI = (P == Q) && (ET * 3 * Q2 <= NT) && !(std::is_same<T, double>::value && P == 5);
-  const int e3 = tq / (3 * Q2), r3 = tq % (3 * Q2), c3 = r3 / Q2, ln3 = r3 % Q2;
-  const bool a3 = tq < ET * 3 * Q2 && e3 < nel;
-  T *const p3 = lds + (a3 ? e3 * ELS + c3 * Q3 : 0);
-  const int lb0 = line_base<Q, 0, Q>(ln3), lb1 = line_base<Q, 1, Q>(ln3), lb2 = line_base<Q, 2, Q>(ln3);
   // Interpolation to the points, one direction at a time, in place.
   if constexpr (FI) {
     if (a3) line_task<T, P, Q, false, 1>(p3 + lb0, tB);
@@ -693,6 +708,35 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
     }
   }
   __syncthreads();
+  if constexpr (MODE == 5) {
+    if (pass == 0) {
+      // the kinematics of u at this point, kept for the du pass
+      if (live) {
+        T Gu[3][3], D[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          Gu[c][0] = G[(c * 2) * Q3 + q];
+          Gu[c][1] = G[(c * 2 + 1) * Q3 + q];
+          Gu[c][2] = v[c * Q3 + q];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int J = 0; J < 3; ++J) D[k][J] = (T)gv[1 + k * 3 + J];
+        Kin<T> k;
+        kinematics(Gu, D, (T)mat_mu(mu0, mu_e, e), (T)mat_mu(lam0, lam_e, e), k);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int j = 0; j < 3; ++j) kA[i][j] = k.A[i][j];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) ktau[m] = k.tau[m];
+        kc = k.c;
+      }
+      __syncthreads();  // every point has read its gradient before du overwrites the frames
+    }
+  }
+  }  // pass
   // Quadrature function, one thread per point, flux written over the gradient
   // (components k = 0, 1 in G, k = 2 in v).
   if (live) {
@@ -730,6 +774,8 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
           tau[sym_index(i, j)] = mu * (hv[i * 3 + j] + hv[j * 3 + i] + hh) + (i == j ? c : 0.0);
         }
       jacobian_qf(Gq, A, tau, c, gv[0], mu, lam, f);
+    } else if constexpr (MODE == 5) {
+      jacobian_qf(Gq, kA, ktau, kc, (T)gv[0], (T)mat_mu(mu0, mu_e, e), (T)mat_mu(lam0, lam_e, e), f);
     } else if constexpr (MODE == 4) {
       double D[3][3];
 #pragma unroll
@@ -1024,71 +1070,6 @@ __global__ void k_traction_load(const double *__restrict__ X, const int32_t *__r
     out[3 * k + 1] = acc[k] * t1;
     out[3 * k + 2] = acc[k] * t2;
   }
-}
-
-// ------------------------------------------------------------------------------------
-// a5': Jacobian action recomputing the linearisation from u and the geometry.
-// ------------------------------------------------------------------------------------
-template <typename T, int P, int Q>
-__global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_recompute(
-    const uint32_t *__restrict__ emap, const double *__restrict__ u, const T *__restrict__ du,
-    const double *__restrict__ geo, const T *__restrict__ tab, double mu0, double lam0,
-    const double *__restrict__ mu_e, const double *__restrict__ lam_e, T *__restrict__ ev, int64_t E) {
-  constexpr int Q3 = QT<Q>::Q3, ET = QT<Q>::ET, NQ = QT<Q>::NQ, NT = QT<Q>::NT, P3 = P * P * P;
-  constexpr int S0 = 9 * Q3, S1 = 6 * Q3;
-  __shared__ T sB[Q * P], sD[Q * Q];
-  __shared__ T lds[ET * (S0 + S1)];
-  const int tq = threadIdx.x, el = tq / Q3, q = tq % Q3;
-  const int64_t tile = xcd_tile();
-  const int64_t e = tile * ET + el;
-  const bool live = tq < NQ && e < E;
-  uint32_t w = 0;
-  if (live && q < P3) w = emap[e * P3 + q];
-  load_tables(sB, tab, TAB_B, Q * P, tq, NT);
-  load_tables(sD, tab, TAB_D, Q * Q, tq, NT);
-  T *a = lds + (live ? el : 0) * S0, *b = lds + ET * S0 + (live ? el : 0) * S1;
-  if (live && q < P3) {
-    gather_node(u, w, false, a, q, P3);
-    gather_node(du, w, true, a + 3 * P3, q, P3);
-  }
-  double gv[NGEO];
-  if (live) {
-    const double *g = geo + tile * NGEO * NQ + tq;
-#pragma unroll
-    for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
-  }
-  __syncthreads();
-  interp<T, P, Q, 6>(a, b, sB, q, live);
-  if (live) {
-    T G6[6][3], Gu[3][3], Gd[3][3], D[3][3];
-    grad_q<T, Q, 6>(b, sD, q, G6);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        Gu[i][k] = G6[i][k];
-        Gd[i][k] = G6[3 + i][k];
-      }
-    const T W = (T)gv[0];
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int J = 0; J < 3; ++J) D[k][J] = (T)gv[1 + k * 3 + J];
-    const T mu = (T)mat_mu(mu0, mu_e, e), lam = (T)mat_mu(lam0, lam_e, e);
-    Kin<T> k;
-    kinematics(Gu, D, mu, lam, k);
-    T f[3][3];
-    jacobian_qf(Gd, k.A, k.tau, k.c, W, mu, lam, f);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int kk = 0; kk < 3; ++kk) a[(i * 3 + kk) * Q3 + q] = f[i][kk];
-  }
-  __syncthreads();
-  grad_t_q<T, Q>(a, sD, q, b, live);
-  __syncthreads();
-  interp_t<T, P, Q, 3>(b, a, sB, q, live);
-  if (live && q < P3) store_record(ev, e, a, q, P3);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1843,7 +1824,7 @@ hipError_t launch_residual(const hpmg_op_s &op, const double *u, double *r, bool
     lines_launch<double, p, q, 4>((unsigned)op.tiles, s, keep_records<double>(op.E, p), op.emap, u,            \
                                   (const double *)nullptr, op.geo, (const double *)nullptr, op.tab64, op.mu,      \
                                   op.lam, op.mu_e, op.lam_e, (double *)op.evec, op.E, (const double *)nullptr,    \
-                                  store ? op.state64 : nullptr, op.flags);                                        \
+                                  store ? op.state64 : nullptr, op.flags, (const double *)nullptr);               \
     hipError_t e = hipGetLastError();                                                            \
     if (e != hipSuccess) return e;                                                               \
     return assemble<double>(op, nullptr, r, s);                                                  \
@@ -1864,22 +1845,23 @@ static hipError_t jacobian_pq(const hpmg_op_s &op, const hpmg_op_s &f, int mode,
     if (mode == HPMG_INITIAL_NATIVE || mode == HPMG_INITIAL_TUNED || mode == HPMG_CURRENT_20) {
       if (mode == HPMG_INITIAL_NATIVE)
         lines_launch<T, P, Q, 1>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr, nullptr);
       else if (mode == HPMG_INITIAL_TUNED)
         lines_launch<T, P, Q, 2>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr, nullptr);
       else
         lines_launch<T, P, Q, 3>(g, s, keep, op.emap, du, nullptr, op.geo, op.sinit, tab, op.mu, op.lam, op.mu_e,
-                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr);
+                                 op.lam_e, ev, op.E, nullptr, nullptr, nullptr, nullptr);
       return hipGetLastError();
     }
   }
   if (mode == HPMG_STORED) {
     lines_launch<T, P, Q, 0>(g, s, keep, op.emap, du, state, nullptr, nullptr, tab, f.mu, f.lam, f.mu_e, f.lam_e,
-                             ev, op.E, stop, nullptr, nullptr);
+                             ev, op.E, stop, nullptr, nullptr, nullptr);
   } else {
-    k_jacobian_recompute<T, P, Q><<<(unsigned)op.tiles, QT<Q>::NT, 0, s>>>(op.emap, u, du, op.geo, tab, op.mu,
-                                                                           op.lam, op.mu_e, op.lam_e, ev, op.E);
+    lines_launch<T, P, Q, 5>(g, s, keep, op.emap, du, (const T *)nullptr, op.geo, (const double *)nullptr, tab,
+                             op.mu, op.lam, op.mu_e, op.lam_e, ev, op.E, (const double *)nullptr,
+                             (double *)nullptr, (unsigned *)nullptr, u);
   }
   return hipGetLastError();
 }
