@@ -68,8 +68,8 @@ def test_host_argument_validation(L):
     assert L.hpmg_op_create(3, 3, 10, 100, fake, None, C.byref(h)) == 0
     nb = C.c_size_t()
     assert L.hpmg_op_workspace_bytes(h, C.byref(nb)) == 0
-    # workspace: tables + map + records + incidence + scratch + 10 + 17 + 17/2 doubles per point
-    assert nb.value > 10 * 27 * (10 + 17) * 8
+    # workspace: tables + map + records + incidence + scratch + 10 + 16 + 16/2 doubles per point
+    assert nb.value > 10 * 27 * (10 + 16) * 8
     assert L.hpmg_residual(h, fake, fake, 1, None) == 4  # workspace not bound
     assert b"workspace" in L.hpmg_last_error()
     assert L.hpmg_op_set_material(h, 1.0, 1.0, fake, None) == 1
