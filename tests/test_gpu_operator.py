@@ -56,6 +56,7 @@ CASES = [  # (n, p, q, faces)
     (3, 2, 4, None),                                   # Q = P + 1
     ((3, 2, 1), 2, 3, None),                           # ragged last tile
     (1, 2, 3, None),                                   # a single element
+    (2, 4, 6, {"x1": (1, 1, 1)}),                      # over-integrated order 4 (Q = P + 1)
 ]
 
 
