@@ -479,10 +479,11 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_qdata(const uint32_t *__restrict_
 // linearisation (FP64 or FP32), with register-blocked 1D contractions.
 //
 // With one thread per point, each 1D contraction would cost a thread one LDS read per
-// input of every output.  Here every contraction stage is run by "line tasks": a task owns one line of points along the contraction direction (for one
-// component), reads the line once, forms all of its outputs in registers from the 1D
-// table (the same for every lane, so it is read through the scalar cache, not LDS) and
-// writes them back in place.  That is one LDS read and one write per point and stage.
+// input of every output.  Here every contraction stage is run by "line tasks": a task
+// owns one line of points along the contraction direction (for one component), reads
+// the line once, forms all of its outputs in registers from the 1D table (the same for
+// every lane, so it is read through the scalar cache, not LDS) and writes them back in
+// place.  That is one LDS read and one write per point and stage.
 // Nodal (P^3) and quadrature (Q^3) arrays share one Q^3 frame per component, indexed
 // i1 + Q i2 + Q^2 i3, so the interpolation stages can work in place.  The pointwise
 // work (state loads, quadrature function, gather, records) keeps the one-thread-per-
@@ -601,141 +602,141 @@ __global__ __launch_bounds__(QT<Q>::NT) void k_jacobian_lines(
   T kA[3][3], ktau[6], kc = T(0);
 #pragma unroll 1
   for (int pass = MODE == 5 ? 0 : 1; pass < 2; ++pass) {
-  if (live && q < P3) {
-    const uint32_t w = emap[e * P3 + q];
-    T x0, x1, x2;
-    if (MODE == 5 && pass == 0) {
-      const double *src = u + (int64_t)(w & EMAP_ID_MASK) * 3;
-      x0 = (T)src[0], x1 = (T)src[1], x2 = (T)src[2];
-    } else {
-      const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
-      x0 = src[0], x1 = src[1], x2 = src[2];
-    }
-    // u is taken whole (the residual, the recompute form's first pass); du has its
-    // constrained components zeroed
-    const uint32_t bc = (MODE == 4 || pass == 0) ? 0u : (w >> EMAP_BC_SHIFT);
-    v[qn] = (bc & 1u) ? T(0) : x0;
-    v[Q3 + qn] = ((bc >> 1) & 1u) ? T(0) : x1;
-    v[2 * Q3 + qn] = ((bc >> 2) & 1u) ? T(0) : x2;
-  }
-  if (live && (MODE != 5 || pass == 0)) {
-    if constexpr (MODE == 0) {
-      const T *s = state + tile * NSTATE * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
-    } else if constexpr (MODE == 3) {
-      gv[0] = __builtin_nontemporal_load(geo + tile * NGEO * NQ + tq);  // W only
-      const double *h = sinit + tile * NINIT * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < 9; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
-#pragma unroll
-      for (int f = 0; f < 10; ++f) hv[9 + f] = __builtin_nontemporal_load(h + (16 + f) * NQ);
-    } else if constexpr (MODE == 4 || MODE == 5) {
-      const double *g = geo + tile * NGEO * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
-    } else {
-      const double *g = geo + tile * NGEO * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
-      const double *h = sinit + tile * NINIT * NQ + tq;
-#pragma unroll
-      for (int f = 0; f < NH; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
-    }
-  }
-  __syncthreads();
-  // Interpolation to the points, one direction at a time, in place.
-  if constexpr (FI) {
-    if (a3) line_task<T, P, Q, false, 1>(p3 + lb0, tB);
-  } else {
-    line_stage<T, Q, 0, P, Q, false, P, P, ET, ELS>(lds, tB, tq, NT, nel);
-  }
-  __syncthreads();
-  if constexpr (FI) {
-    if (a3) line_task<T, P, Q, false, Q>(p3 + lb1, tB);
-  } else {
-    line_stage<T, Q, 1, P, Q, false, Q, P, ET, ELS>(lds, tB, tq, NT, nel);
-  }
-  __syncthreads();
-  if constexpr (FI) {
-    if (a3) line_task<T, P, Q, false, Q2>(p3 + lb2, tB);
-  } else {
-    line_stage<T, Q, 2, P, Q, false, Q, Q, ET, ELS>(lds, tB, tq, NT, nel);
-  }
-  __syncthreads();
-  // Collocated derivative in the three directions: G[c][k] = D_k v[c] for k = 0, 1 into
-  // G, then (once every x and y line has read v) D_z v[c] in place over v[c].
-  {
-    constexpr int TASKS = 6 * Q2;
-    for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 2, k = ck % 2, ln = r % Q2;
-      if (te >= nel) break;
-      const T *src = lds + te * ELS + c * Q3;
-      T *dst = lds + te * ELS + (3 + ck) * Q3;
-      T x[Q], y[Q];
-      if (k == 0) {
-        const int b0 = line_base<Q, 0, Q>(ln);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = src[b0 + i];
-        line_apply<T, Q, Q, false>(tD, x, y);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) dst[b0 + i] = y[i];
+    if (live && q < P3) {
+      const uint32_t w = emap[e * P3 + q];
+      T x0, x1, x2;
+      if (MODE == 5 && pass == 0) {
+        const double *src = u + (int64_t)(w & EMAP_ID_MASK) * 3;
+        x0 = (T)src[0], x1 = (T)src[1], x2 = (T)src[2];
       } else {
-        const int b1 = line_base<Q, 1, Q>(ln);
+        const T *src = du + (int64_t)(w & EMAP_ID_MASK) * 3;
+        x0 = src[0], x1 = src[1], x2 = src[2];
+      }
+      // u is taken whole (the residual, the recompute form's first pass); du has its
+      // constrained components zeroed
+      const uint32_t bc = (MODE == 4 || pass == 0) ? 0u : (w >> EMAP_BC_SHIFT);
+      v[qn] = (bc & 1u) ? T(0) : x0;
+      v[Q3 + qn] = ((bc >> 1) & 1u) ? T(0) : x1;
+      v[2 * Q3 + qn] = ((bc >> 2) & 1u) ? T(0) : x2;
+    }
+    if (live && (MODE != 5 || pass == 0)) {
+      if constexpr (MODE == 0) {
+        const T *s = state + tile * NSTATE * NQ + tq;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) x[i] = src[b1 + i * Q];
+        for (int f = 0; f < NSTATE; ++f) sv[f] = __builtin_nontemporal_load(s + f * NQ);
+      } else if constexpr (MODE == 3) {
+        gv[0] = __builtin_nontemporal_load(geo + tile * NGEO * NQ + tq);  // W only
+        const double *h = sinit + tile * NINIT * NQ + tq;
+#pragma unroll
+        for (int f = 0; f < 9; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
+#pragma unroll
+        for (int f = 0; f < 10; ++f) hv[9 + f] = __builtin_nontemporal_load(h + (16 + f) * NQ);
+      } else if constexpr (MODE == 4 || MODE == 5) {
+        const double *g = geo + tile * NGEO * NQ + tq;
+#pragma unroll
+        for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
+      } else {
+        const double *g = geo + tile * NGEO * NQ + tq;
+#pragma unroll
+        for (int f = 0; f < NGEO; ++f) gv[f] = __builtin_nontemporal_load(g + f * NQ);
+        const double *h = sinit + tile * NINIT * NQ + tq;
+#pragma unroll
+        for (int f = 0; f < NH; ++f) hv[f] = __builtin_nontemporal_load(h + f * NQ);
+      }
+    }
+    __syncthreads();
+    // Interpolation to the points, one direction at a time, in place.
+    if constexpr (FI) {
+      if (a3) line_task<T, P, Q, false, 1>(p3 + lb0, tB);
+    } else {
+      line_stage<T, Q, 0, P, Q, false, P, P, ET, ELS>(lds, tB, tq, NT, nel);
+    }
+    __syncthreads();
+    if constexpr (FI) {
+      if (a3) line_task<T, P, Q, false, Q>(p3 + lb1, tB);
+    } else {
+      line_stage<T, Q, 1, P, Q, false, Q, P, ET, ELS>(lds, tB, tq, NT, nel);
+    }
+    __syncthreads();
+    if constexpr (FI) {
+      if (a3) line_task<T, P, Q, false, Q2>(p3 + lb2, tB);
+    } else {
+      line_stage<T, Q, 2, P, Q, false, Q, Q, ET, ELS>(lds, tB, tq, NT, nel);
+    }
+    __syncthreads();
+    // Collocated derivative in the three directions: G[c][k] = D_k v[c] for k = 0, 1 into
+    // G, then (once every x and y line has read v) D_z v[c] in place over v[c].
+    {
+      constexpr int TASKS = 6 * Q2;
+      for (int t = tq; t < ET * TASKS; t += NT) {
+        const int te = t / TASKS, r = t % TASKS, ck = r / Q2, c = ck / 2, k = ck % 2, ln = r % Q2;
+        if (te >= nel) break;
+        const T *src = lds + te * ELS + c * Q3;
+        T *dst = lds + te * ELS + (3 + ck) * Q3;
+        T x[Q], y[Q];
+        if (k == 0) {
+          const int b0 = line_base<Q, 0, Q>(ln);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) x[i] = src[b0 + i];
+          line_apply<T, Q, Q, false>(tD, x, y);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) dst[b0 + i] = y[i];
+        } else {
+          const int b1 = line_base<Q, 1, Q>(ln);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) x[i] = src[b1 + i * Q];
+          line_apply<T, Q, Q, false>(tD, x, y);
+#pragma unroll
+          for (int i = 0; i < Q; ++i) dst[b1 + i * Q] = y[i];
+        }
+      }
+    }
+    __syncthreads();
+    if constexpr (FI) {
+      if (a3) line_task<T, Q, Q, false, Q2>(p3 + lb2, tD);
+    } else {
+      constexpr int TASKS = 3 * Q2;
+      for (int t = tq; t < ET * TASKS; t += NT) {
+        const int te = t / TASKS, r = t % TASKS, c = r / Q2, ln = r % Q2;
+        if (te >= nel) break;
+        T *p = lds + te * ELS + c * Q3 + line_base<Q, 2, Q>(ln);
+        T x[Q], y[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) x[i] = p[i * Q2];
         line_apply<T, Q, Q, false>(tD, x, y);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) dst[b1 + i * Q] = y[i];
+        for (int i = 0; i < Q; ++i) p[i * Q2] = y[i];
       }
     }
-  }
-  __syncthreads();
-  if constexpr (FI) {
-    if (a3) line_task<T, Q, Q, false, Q2>(p3 + lb2, tD);
-  } else {
-    constexpr int TASKS = 3 * Q2;
-    for (int t = tq; t < ET * TASKS; t += NT) {
-      const int te = t / TASKS, r = t % TASKS, c = r / Q2, ln = r % Q2;
-      if (te >= nel) break;
-      T *p = lds + te * ELS + c * Q3 + line_base<Q, 2, Q>(ln);
-      T x[Q], y[Q];
+    __syncthreads();
+    if constexpr (MODE == 5) {
+      if (pass == 0) {
+        // the kinematics of u at this point, kept for the du pass
+        if (live) {
+          T Gu[3][3], D[3][3];
 #pragma unroll
-      for (int i = 0; i < Q; ++i) x[i] = p[i * Q2];
-      line_apply<T, Q, Q, false>(tD, x, y);
+          for (int c = 0; c < 3; ++c) {
+            Gu[c][0] = G[(c * 2) * Q3 + q];
+            Gu[c][1] = G[(c * 2 + 1) * Q3 + q];
+            Gu[c][2] = v[c * Q3 + q];
+          }
 #pragma unroll
-      for (int i = 0; i < Q; ++i) p[i * Q2] = y[i];
-    }
-  }
-  __syncthreads();
-  if constexpr (MODE == 5) {
-    if (pass == 0) {
-      // the kinematics of u at this point, kept for the du pass
-      if (live) {
-        T Gu[3][3], D[3][3];
+          for (int k = 0; k < 3; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          Gu[c][0] = G[(c * 2) * Q3 + q];
-          Gu[c][1] = G[(c * 2 + 1) * Q3 + q];
-          Gu[c][2] = v[c * Q3 + q];
+            for (int J = 0; J < 3; ++J) D[k][J] = (T)gv[1 + k * 3 + J];
+          Kin<T> k;
+          kinematics(Gu, D, (T)mat_mu(mu0, mu_e, e), (T)mat_mu(lam0, lam_e, e), k);
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) kA[i][j] = k.A[i][j];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) ktau[m] = k.tau[m];
+          kc = k.c;
         }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-#pragma unroll
-          for (int J = 0; J < 3; ++J) D[k][J] = (T)gv[1 + k * 3 + J];
-        Kin<T> k;
-        kinematics(Gu, D, (T)mat_mu(mu0, mu_e, e), (T)mat_mu(lam0, lam_e, e), k);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-          for (int j = 0; j < 3; ++j) kA[i][j] = k.A[i][j];
-#pragma unroll
-        for (int m = 0; m < 6; ++m) ktau[m] = k.tau[m];
-        kc = k.c;
+        __syncthreads();  // every point has read its gradient before du overwrites the frames
       }
-      __syncthreads();  // every point has read its gradient before du overwrites the frames
     }
-  }
   }  // pass
   // Quadrature function, one thread per point, flux written over the gradient
   // (components k = 0, 1 in G, k = 2 in v).
