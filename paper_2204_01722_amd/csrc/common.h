@@ -142,7 +142,7 @@ hipError_t launch_fcg_dir(int64_t n, double *sc, int it, const double *z, double
 // ell_pcg_blocks(nn, node_major) workgroups write pq_part.  nn = 0 runs only the
 // stopping test of the iteration before `it` (to close a batch).  node_major: blocks
 // held entry-major over the nodes and a thread per node (else a node's rows contiguous
-// and a thread per row), the same choice as the build's.
+// and a thread per row), the same choice as the block build's (launch_ell_build).
 // By default coarse levels of at least this many nodes are node-major.
 constexpr int64_t ELL_NODE_MAJOR_MIN = 65536;
 int ell_pcg_blocks(int64_t nn, bool node_major);
