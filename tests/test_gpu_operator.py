@@ -227,6 +227,38 @@ def test_inverted_geometry_flag():
     assert H.fine.query_flags() & 1
 
 
+@pytest.mark.parametrize("p", [2, 4])
+def test_nonfinite_displacement_flag(p):
+    """A NaN in the displacement makes J non-finite at the quadrature points of the
+    elements around it: the residual raises the non-finite bit, not the inverted one, and
+    a finite displacement afterwards leaves the (read-and-cleared) word at zero."""
+    import torch
+    print_case("nonfinite_u", p=p)
+    m, H = _setup(2, p, jitter=0.05)
+    u = inputs.config1_u(m, amplitude=0.05)
+    assert H.fine.query_flags() == 0
+    bad = u.copy()
+    bad[m.elem_nodes[0, 0], 1] = np.nan
+    H.fine.residual(_dev(bad), store_state=False)
+    torch.cuda.synchronize()
+    f = H.fine.query_flags()
+    assert f & 2 and not f & 1, f
+    H.fine.residual(_dev(u), store_state=False)
+    torch.cuda.synchronize()
+    assert H.fine.query_flags() == 0
+
+
+def test_nonfinite_geometry_flag():
+    print_case("nonfinite_geometry")
+    from paper_2204_01722_amd.problem import Hierarchy
+    m = inputs.box_mesh(2, 2, jitter=0.0)
+    c = m.coords.copy()
+    c[m.elem_nodes[0, 13], 2] = np.nan
+    m.coords = c
+    H = Hierarchy(m, [2])
+    assert H.fine.query_flags() & 2
+
+
 @pytest.mark.parametrize("mode", ["stored", "recompute"])
 def test_vjp(mode):
     print_case("vjp", mode=mode)
