@@ -57,6 +57,8 @@ CASES = [  # (n, p, q, faces)
     ((3, 2, 1), 2, 3, None),                           # ragged last tile
     (1, 2, 3, None),                                   # a single element
     (2, 4, 6, {"x1": (1, 1, 1)}),                      # over-integrated order 4 (Q = P + 1)
+    (3, 1, 3, {"y0": (1, 1, 1)}),                      # over-integrated order 1
+    ((2, 2, 3), 3, 5, {"z0": (0, 0, 1)}),              # over-integrated order 3, a roller face
 ]
 
 
@@ -125,7 +127,7 @@ def test_initial_configuration_jacobian(n, p, q, faces):
     assert op.query_flags() == 0
 
 
-@pytest.mark.parametrize("n,p,q,faces", CASES[:5])
+@pytest.mark.parametrize("n,p,q,faces", CASES[:5] + CASES[-2:])
 def test_diagonal(n, p, q, faces):
     print_case("diagonal", n=n, p=p, q=q, faces=faces)
     m, H = _setup(n, p, faces=faces, q=q)
