@@ -353,7 +353,8 @@ typedef struct {
                            0: always the lifted start with the Euler predictor */
   int lin_norm;         /* (0) norm of the FCG stopping test: 0: ||r||_2 <= lin_rtol ||r0||_2;
                            1: the natural norm of the preconditioned system (Section III-A),
-                           sqrt(r^T M^-1 r) <= lin_rtol sqrt(r0^T M^-1 r0), M^-1 one V-cycle */
+                           sqrt(r^T M^-1 r) <= lin_rtol sqrt(r0^T M^-1 r0), M^-1 one V-cycle;
+                           any other value: HPMG_ERR_ARG */
 } hpmg_newton_params;
 void hpmg_newton_default_params(hpmg_newton_params *p);
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext,

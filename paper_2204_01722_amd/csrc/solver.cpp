@@ -826,14 +826,19 @@ static int newton_at_load(hpmg_op fine, hpmg_mg_s *mg, double *u, const double *
 
 int hpmg_newton_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext, int n_steps,
                       const hpmg_newton_params *prm, const double *const *seeds, double *stats, void *stream) {
+  // parameters first: nothing behind the handles is touched before they pass
+  if (!u || !lift || !prm || !seeds || !stats) return fail(HPMG_ERR_ARG, "newton_solve: null argument");
+  if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "newton_solve: 1 <= n_steps <= 60");
+  if (prm->max_total_newton < 1 || prm->max_total_krylov < 1)
+    return fail(HPMG_ERR_ARG, "newton_solve: the total iteration budgets must be positive");
+  if (prm->max_newton < 1 || prm->lin_maxit < 1 || !(prm->rtol > 0.0) || !(prm->lin_rtol > 0.0))
+    return fail(HPMG_ERR_ARG, "newton_solve: iteration limits and tolerances must be positive");
+  if (prm->lin_norm != 0 && prm->lin_norm != 1)
+    return fail(HPMG_ERR_ARG, "newton_solve: lin_norm must be 0 (2-norm) or 1 (natural norm)");
   int st = mg_check(mg, "newton_solve");
   if (st) return st;
   if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "newton_solve: operator is not the mg fine level");
-  if (!u || !lift || !prm || !seeds || !stats) return fail(HPMG_ERR_ARG, "newton_solve: null argument");
-  if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "newton_solve: 1 <= n_steps <= 60");
   if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "newton_solve: call qdata_setup first");
-  if (prm->max_total_newton < 1 || prm->max_total_krylov < 1)
-    return fail(HPMG_ERR_ARG, "newton_solve: the total iteration budgets must be positive");
   hipStream_t s = S(stream);
   const int64_t n = mg->lv[0].n;
   for (int k = 0; k < 4 + n_steps; ++k) stats[k] = 0.0;

@@ -88,3 +88,29 @@ def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError, match="no fallback"):
         binding.lib()
+
+
+def test_newton_parameters_rejected_before_any_handle_is_used(L):
+    """The Newton driver checks its parameters before it looks behind the operator or
+    multigrid handles, so bad values are reported without a GPU."""
+    from paper_2204_01722_amd import binding
+    fake = C.c_void_p(0x1000)  # never dereferenced
+    stats = (C.c_double * 64)()
+    seeds = (C.c_void_p * 4)()
+
+    def call(mg=fake, **kw):
+        prm = binding.NewtonParams()
+        L.hpmg_newton_default_params(C.byref(prm))
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        return L.hpmg_newton_solve(fake, mg, fake, fake, None, 1, C.byref(prm), seeds, stats, None)
+
+    bad = [{"lin_norm": 2}, {"lin_norm": -1}, {"rtol": 0.0}, {"lin_rtol": float("nan")},
+           {"max_newton": 0}, {"lin_maxit": 0}, {"max_total_newton": 0}, {"max_total_krylov": 0}]
+    for kw in bad:
+        assert call(**kw) == 1, kw
+        assert L.hpmg_last_error().startswith(b"newton_solve:"), kw
+    # both norms pass the parameter checks and stop at the (null) multigrid handle
+    for norm in (0, 1):
+        assert call(mg=None, lin_norm=norm) == 1
+        assert b"null multigrid handle" in L.hpmg_last_error()
