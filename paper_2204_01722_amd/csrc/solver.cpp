@@ -971,14 +971,15 @@ int hpmg_lbfgs_workspace_bytes(hpmg_mg mg, int memory, size_t *bytes) {
 int hpmg_lbfgs_solve(hpmg_op fine, hpmg_mg mg, double *u, const double *lift, const double *f_ext, int n_steps,
                      const hpmg_lbfgs_params *prm, const double *const *seeds, void *workspace,
                      size_t workspace_bytes, double *stats, void *stream) {
-  int st = mg_check(mg, "lbfgs_solve");
-  if (st) return st;
-  if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "lbfgs_solve: operator is not the mg fine level");
+  // parameters first: nothing behind the handles is touched before they pass
   if (!u || !lift || !prm || !seeds || !stats || !workspace) return fail(HPMG_ERR_ARG, "lbfgs_solve: null argument");
   if (n_steps < 1 || n_steps > 60) return fail(HPMG_ERR_ARG, "lbfgs_solve: 1 <= n_steps <= 60");
   const int m = prm->memory;
   if (m < 1 || m > 32) return fail(HPMG_ERR_ARG, "lbfgs_solve: 1 <= memory <= 32");
   if (!(prm->rtol > 0.0) || prm->max_its < 1) return fail(HPMG_ERR_ARG, "lbfgs_solve: rtol > 0, max_its >= 1");
+  int st = mg_check(mg, "lbfgs_solve");
+  if (st) return st;
+  if (!fine || fine != mg->lv[0].op) return fail(HPMG_ERR_ARG, "lbfgs_solve: operator is not the mg fine level");
   if (!fine->geo_ready) return fail(HPMG_ERR_ARG, "lbfgs_solve: call qdata_setup first");
   const int64_t n = mg->lv[0].n;
   if (workspace_bytes < lbfgs_bytes(n, m)) return fail(HPMG_ERR_WORKSPACE, "lbfgs_solve: workspace too small");

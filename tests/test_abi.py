@@ -114,3 +114,23 @@ def test_newton_parameters_rejected_before_any_handle_is_used(L):
     for norm in (0, 1):
         assert call(mg=None, lin_norm=norm) == 1
         assert b"null multigrid handle" in L.hpmg_last_error()
+
+
+def test_lbfgs_parameters_rejected_before_any_handle_is_used(L):
+    from paper_2204_01722_amd import binding
+    fake = C.c_void_p(0x1000)  # never dereferenced
+    stats = (C.c_double * 64)()
+    seeds = (C.c_void_p * 4)()
+
+    def call(mg=fake, **kw):
+        prm = binding.LbfgsParams()
+        L.hpmg_lbfgs_default_params(C.byref(prm))
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        return L.hpmg_lbfgs_solve(fake, mg, fake, fake, None, 1, C.byref(prm), seeds, fake, 1 << 20, stats, None)
+
+    for kw in ({"memory": 0}, {"memory": 33}, {"rtol": 0.0}, {"rtol": float("nan")}, {"max_its": 0}):
+        assert call(**kw) == 1, kw
+        assert L.hpmg_last_error().startswith(b"lbfgs_solve:"), kw
+    assert call(mg=None) == 1
+    assert b"null multigrid handle" in L.hpmg_last_error()
