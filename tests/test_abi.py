@@ -134,3 +134,23 @@ def test_lbfgs_parameters_rejected_before_any_handle_is_used(L):
         assert L.hpmg_last_error().startswith(b"lbfgs_solve:"), kw
     assert call(mg=None) == 1
     assert b"null multigrid handle" in L.hpmg_last_error()
+
+
+def test_mg_parameters_rejected_before_any_level_is_used(L):
+    from paper_2204_01722_amd import binding
+    levels = (C.c_void_p * 3)(0x1000, 0x2000, 0x3000)  # never dereferenced
+    out = C.c_void_p()
+
+    def call(n_levels=3, **kw):
+        prm = binding.MGParams()
+        L.hpmg_mg_default_params(C.byref(prm))
+        for k, v in kw.items():
+            setattr(prm, k, v)
+        return L.hpmg_mg_create(levels, n_levels, C.byref(prm), C.byref(out))
+
+    bad = [{"n_levels": 1}, {"precision": 7}, {"cheb_degree": 0}, {"cheb_lo": 0.0}, {"cheb_hi": 0.05},
+           {"lanczos_its": 0}, {"coarse_maxit": 0}, {"coarse_block_layout": 2}, {"coarse_block_layout": -2}]
+    for kw in bad:
+        assert call(**kw) == 1, kw
+        assert L.hpmg_last_error().startswith(b"mg_create:"), kw
+        assert out.value is None
