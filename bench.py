@@ -507,7 +507,7 @@ def main():
     achieved = nbytes / (ms * 1e-3) / 1e9
     print(f"[bench] Q4 f64 stored: {ms:.4f} ms, {value:.2f} GDoF/s", file=sys.stderr, flush=True)
 
-    # the same loop repeated: the spread of the headline on this box
+    # the same loop repeated: the spread of the headline on this machine
     variants = {"headline_repeats_ms": [time_op(q4.apply("f64", "stored"), args.steps, 1, stream) for _ in range(4)]}
     if not args.only_headline:
         for prec, mode in (("f32", "stored"), ("f64", "recompute"), ("f32", "recompute")):
