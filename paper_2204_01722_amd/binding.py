@@ -568,6 +568,28 @@ class PMG:
                 raise HpmgError(st, f"{err} (statistics so far: {res})") from None
         return u, res
 
+    def newton_checkpointed(self, u, lift, n_steps, seeds, path, f_ext=None, stop_after=None, **newton_kw):
+        """Newton load stepping one load level per driver call, with the state saved to
+        ``path`` (``.npz``) after every converged level and a run resumed after the last
+        saved level (see :mod:`.checkpoint`).  Level k adds ``lift / n_steps`` to ``u``
+        and balances ``(k / n_steps) f_ext``: the same levels as :meth:`newton` with
+        ``n_steps``, each starting from the previous level's state with the Euler
+        predictor; the iteration budgets of ``newton_kw`` apply per level.  ``stop_after``
+        ends the run at that level.  Returns ``u``, the first level run, the level
+        reached and the per-level statistics of :meth:`newton`."""
+        from . import checkpoint
+        _vec(u, self.levels[0].n_nodes, torch.float64, self.levels[0].device, "u")
+        lift = self._fine_vec(lift, "lift")
+        f_ext = None if f_ext is None else self._fine_vec(f_ext, "f_ext")
+        tag = checkpoint.fingerprint(lift, f_ext, extra=f"newton/{self.levels[0].n_nodes}/{n_steps}")
+        step_lift = lift / n_steps
+
+        def step(k, v):
+            fk = None if f_ext is None else f_ext * (k / n_steps)
+            return self.newton(v, step_lift, 1, seeds, f_ext=fk, **newton_kw)[1]
+
+        return checkpoint.run_load_steps(step, u, n_steps, path, tag, stop_after)
+
     def set_state(self, u):
         """Stores the linearisations of rediscretised coarse levels at the injection of
         ``u`` (no-op for Galerkin levels)."""

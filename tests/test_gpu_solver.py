@@ -554,3 +554,61 @@ def test_newton_uniaxial_stress_by_traction():
     u = zero.clone()
     u, st = PMG(H.ops, precision="f32").lbfgs(u, zero, 3, H.seeds(7), rtol=1e-11, f_ext=f_ext)
     assert np.abs(t2n(u) - exact).max() < 1e-9
+
+
+def test_newton_checkpointed_resume(tmp_path):
+    """Load stepping split over driver calls with a checkpoint file: a traction load
+    stopped after level 2 of 3 sits at the closed-form state of 2/3 of the traction,
+    and the resumed run reaches the full-traction state; a clamped box displaced in two
+    levels, stopped after the first and resumed, reaches the oracle's answer."""
+    import torch
+    from scipy.optimize import fsolve
+    from paper_2204_01722_amd.binding import PMG
+    from paper_2204_01722_amd.problem import Hierarchy
+    print_case("newton_checkpointed")
+    faces = {"x0": (1, 0, 0), "y0": (0, 1, 0), "z0": (0, 0, 1)}
+    m = inputs.box_mesh(2, 2, jitter=0.08)
+    H = Hierarchy(m, [2, 1], faces=faces)
+    loaded = [(1 + 2 * (ey + 2 * ez), 1) for ez in range(2) for ey in range(2)]
+    T = 0.12
+    f_ext = H.fine.external_load(None, H.coords, loaded, (T, 0.0, 0.0))
+
+    def uniaxial_stress(t):
+        def eqs(x):
+            l1, l2 = x
+            lj = np.log(l1 * l2 * l2)
+            return [MU * (l1 - 1 / l1) + LAM * lj / l1 - t, MU * (l2 - 1 / l2) + LAM * lj / l2]
+        l1, l2 = fsolve(eqs, [1.1, 0.97], xtol=1e-13)
+        return m.coords * np.array([l1 - 1.0, l2 - 1.0, l2 - 1.0])
+
+    zero = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    pmg = PMG(H.ops, precision="f64")
+    path = str(tmp_path / "traction.npz")
+    kw = dict(rtol=1e-11, lin_rtol=1e-8)
+    u, first, level, st = pmg.newton_checkpointed(zero.clone(), zero, 3, H.seeds(7), path, f_ext=f_ext,
+                                                  stop_after=2, **kw)
+    assert (first, level, len(st)) == (1, 2, 2)
+    assert np.abs(t2n(u) - uniaxial_stress(2 * T / 3)).max() < 1e-9
+    u, first, level, st = pmg.newton_checkpointed(zero.clone(), zero, 3, H.seeds(7), path, f_ext=f_ext, **kw)
+    assert (first, level, len(st)) == (3, 3, 1)
+    assert np.abs(t2n(u) - uniaxial_stress(T)).max() < 1e-9
+    print(f"[newton_checkpointed] traction stats={st}", flush=True)
+
+    faces = {"x0": (1, 1, 1), "x1": (1, 1, 1)}
+    m = inputs.box_mesh(2, 4, jitter=0.05)
+    H = Hierarchy(m, [4, 2, 1], faces=faces)
+    lift_np = inputs.affine_lifting(m, (0.2, 0.0, 0.0))
+    mask = inputs.face_mask(m, faces)
+    d = fem.make_disc(m.coords, m.elem_nodes, m.P)
+    ref, _ = omg.newton_load_steps(d, MU, LAM, mask, lift_np, 2,
+                                   lambda K, rhs: spla.spsolve(K.tocsc(), rhs), rtol=1e-10)
+    pmg = PMG(H.ops, precision="f64")
+    path = str(tmp_path / "lift.npz")
+    zero = torch.zeros(m.n_nodes, 3, dtype=torch.float64, device="cuda")
+    pmg.newton_checkpointed(zero.clone(), _dev(lift_np), 2, H.seeds(7), path, stop_after=1, rtol=1e-10,
+                            lin_rtol=1e-4)
+    u, first, level, st = pmg.newton_checkpointed(zero.clone(), _dev(lift_np), 2, H.seeds(7), path,
+                                                  rtol=1e-10, lin_rtol=1e-4)
+    assert (first, level) == (2, 2)
+    assert rel(t2n(u), ref) < 1e-8, rel(t2n(u), ref)
+    print(f"[newton_checkpointed] lift stats={st}", flush=True)
