@@ -456,6 +456,8 @@ def main():
                          "times each, for a profiler")
     ap.add_argument("--coarse-iteration", type=str, default=None, metavar="N1,N2,...",
                     help="only time one coarse PCG iteration on the N^3 boxes (Q1 level of (N+1)^3 nodes)")
+    ap.add_argument("--jsonl", type=str, default=None, metavar="PATH",
+                    help="also append the record, with the run's arguments and time, to a JSON-lines log")
     ap.add_argument("--pmg-strain", type=float, default=0.10,
                     help="compressive strain of the multiscale block (0.10: solved on every mesh up to 80^3)")
     args = ap.parse_args()
@@ -589,6 +591,18 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    if args.jsonl:
+        append_jsonl(args.jsonl, out, vars(args))
+
+
+def append_jsonl(path, record, run_args):
+    """Appends ``record`` with the run's arguments, wall-clock time and host CPU count as
+    one line of a JSON-lines log (one record per run)."""
+    import datetime
+    line = dict(record, run={"args": run_args, "host_cpus": os.cpu_count(),
+                             "time": datetime.datetime.now(datetime.timezone.utc).isoformat()})
+    with open(path, "a") as f:
+        f.write(json.dumps(line) + "\n")
 
 
 if __name__ == "__main__":

@@ -39,3 +39,15 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=300)
     assert res.returncode == 2
     assert "one GPU" in res.stderr
+
+
+def test_jsonl_log_appends_one_record_per_run(tmp_path):
+    path = str(tmp_path / "runs.jsonl")
+    rec = {"metric": "m", "value": 1.5, "roofline": {"frac": 0.5}}
+    bench.append_jsonl(path, rec, {"steps": 20, "warmup": 5})
+    bench.append_jsonl(path, dict(rec, value=2.5), {"steps": 10, "warmup": 2})
+    lines = [json.loads(x) for x in open(path).read().splitlines()]
+    assert [x["value"] for x in lines] == [1.5, 2.5]
+    assert lines[0]["roofline"] == {"frac": 0.5} and lines[1]["run"]["args"] == {"steps": 10, "warmup": 2}
+    assert lines[0]["run"]["host_cpus"] == os.cpu_count() and "time" in lines[0]["run"]
+    assert "run" not in rec  # the printed record is left as it is
