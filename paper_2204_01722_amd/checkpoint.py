@@ -34,9 +34,14 @@ def fingerprint(*arrays, extra="") -> str:
 def save(path: str, u: torch.Tensor, level: int, n_steps: int, tag: str) -> None:
     """Writes the checkpoint of load level ``level`` (of ``n_steps``) atomically."""
     tmp = f"{path}.tmp.npz"
-    np.savez(tmp, u=u.detach().cpu().numpy(), level=np.int64(level), n_steps=np.int64(n_steps),
-             tag=np.array(tag), format=np.int64(FORMAT))
-    os.replace(tmp, path)
+    try:
+        np.savez(tmp, u=u.detach().cpu().numpy(), level=np.int64(level), n_steps=np.int64(n_steps),
+                 tag=np.array(tag), format=np.int64(FORMAT))
+        os.replace(tmp, path)
+    except BaseException:
+        if os.path.exists(tmp):
+            os.remove(tmp)
+        raise
 
 
 def load(path: str, shape, n_steps: int, tag: str):

@@ -91,3 +91,22 @@ def test_fingerprint_tells_problems_apart():
     assert checkpoint.fingerprint(a, None) != checkpoint.fingerprint(b, None)
     assert checkpoint.fingerprint(a, None) != checkpoint.fingerprint(a, a)
     assert checkpoint.fingerprint(a, None, extra="x") != checkpoint.fingerprint(a, None, extra="y")
+
+
+def test_a_failed_write_keeps_the_previous_checkpoint(tmp_path, monkeypatch):
+    path = str(tmp_path / "ck.npz")
+    checkpoint.run_load_steps(_step, _u0(), 4, path, tag="f", stop_after=2)
+    real = np.savez
+
+    def broken(file, **arrays):
+        real(file, **arrays)
+        raise OSError("disk full")
+
+    monkeypatch.setattr(checkpoint.np, "savez", broken)
+    with pytest.raises(OSError, match="disk full"):
+        checkpoint.run_load_steps(_step, _u0(), 4, path, tag="f")
+    monkeypatch.undo()
+    assert os.listdir(tmp_path) == ["ck.npz"]
+    assert checkpoint.load(path, (17, 3), 4, "f")[1] == 2
+    u, first, level, _ = checkpoint.run_load_steps(_step, _u0(), 4, path, tag="f")
+    assert (first, level) == (3, 4) and torch.equal(u, _full(4))
