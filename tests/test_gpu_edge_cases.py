@@ -71,11 +71,11 @@ def test_reference_configuration(p):
     du = inputs.random_vector(m.n_nodes, 2)
     d = fem.make_disc(m.coords, m.elem_nodes, m.P)
     y_ref = fem.jacobian_apply(d, u, du, MU, LAM)
-    e2, _ = _errs("J(0) du", t2n(op.jacobian(_dev(du), "f64")), y_ref)
-    assert e2 < TOL64
+    e2, einf = _errs("J(0) du", t2n(op.jacobian(_dev(du), "f64")), y_ref)
+    assert max(e2, einf) < TOL64
     op.state_cast_f32()
-    e2, _ = _errs("J(0) du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
-    assert e2 < TOL32
+    e2, einf = _errs("J(0) du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
+    assert max(e2, einf) < TOL32
     # rigid translations are in the null space
     t = np.tile([1.0, -2.0, 0.5], (m.n_nodes, 1))
     yt = t2n(op.jacobian(_dev(t), "f64"))
@@ -101,12 +101,12 @@ def test_small_strain(amplitude, p):
     r_ref = fem.residual(d, u, MU, LAM, mask)
     y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
     r = t2n(op.residual(_dev(u), store_state=True))
-    e2, _ = _errs("residual", r, r_ref)
-    assert e2 < TOL64
-    e2, _ = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64", "stored")), y_ref)
-    assert e2 < TOL64
-    e2, _ = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=_dev(u))), y_ref)
-    assert e2 < TOL64
+    e2, einf = _errs("residual", r, r_ref)
+    assert max(e2, einf) < TOL64
+    e2, einf = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64", "stored")), y_ref)
+    assert max(e2, einf) < TOL64
+    e2, einf = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=_dev(u))), y_ref)
+    assert max(e2, einf) < TOL64
     # the residual is the linear-elastic one to O(|u|^2)
     y_lin = fem.jacobian_apply(d, np.zeros_like(u), u, MU, LAM, mask)
     assert rel(r, y_lin) < 50 * amplitude
@@ -129,10 +129,10 @@ def test_rigid_rotation(p):
     d = fem.make_disc(m.coords, m.elem_nodes, m.P)
     w = inputs.random_vector(m.n_nodes, 4)
     y_ref = fem.jacobian_apply(d, np.zeros_like(u), w @ R, MU, LAM) @ R.T
-    e2, _ = _errs("J(R) w stored", t2n(op.jacobian(_dev(w), "f64")), y_ref)
-    assert e2 < TOL64
-    e2, _ = _errs("J(R) w recompute", t2n(op.jacobian(_dev(w), "f64", "recompute", u=_dev(u))), y_ref)
-    assert e2 < TOL64
+    e2, einf = _errs("J(R) w stored", t2n(op.jacobian(_dev(w), "f64")), y_ref)
+    assert max(e2, einf) < TOL64
+    e2, einf = _errs("J(R) w recompute", t2n(op.jacobian(_dev(w), "f64", "recompute", u=_dev(u))), y_ref)
+    assert max(e2, einf) < TOL64
     # the oracle's own tangent at the rotated state agrees with the rotated stiffness
     assert rel(fem.jacobian_apply(d, u, w, MU, LAM), y_ref) < 1e-12
     assert op.query_flags() == 0
@@ -172,13 +172,13 @@ def test_near_inversion():
     r_ref = fem.residual(d, u, MU, LAM, mask)
     y_ref = fem.jacobian_apply(d, u, du, MU, LAM, mask)
     ut = _dev(u)
-    e2, _ = _errs("residual", t2n(op.residual(ut, store_state=True)), r_ref)
-    assert e2 < TOL64
-    e2, _ = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64")), y_ref)
-    assert e2 < TOL64
-    e2, _ = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=ut)), y_ref)
-    assert e2 < TOL64
+    e2, einf = _errs("residual", t2n(op.residual(ut, store_state=True)), r_ref)
+    assert max(e2, einf) < TOL64
+    e2, einf = _errs("J du stored", t2n(op.jacobian(_dev(du), "f64")), y_ref)
+    assert max(e2, einf) < TOL64
+    e2, einf = _errs("J du recompute", t2n(op.jacobian(_dev(du), "f64", "recompute", u=ut)), y_ref)
+    assert max(e2, einf) < TOL64
     op.state_cast_f32()
-    e2, _ = _errs("J du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
-    assert e2 < TOL32
+    e2, einf = _errs("J du FP32", t2n(op.jacobian(_dev(du).float(), "f32")), y_ref)
+    assert max(e2, einf) < TOL32
     assert op.query_flags() == 0
