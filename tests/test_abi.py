@@ -33,7 +33,9 @@ def test_exports_every_declared_symbol(L):
     assert set(binding.EXPORTED) == set(names)
 
 
-@pytest.mark.parametrize("P,Q", [(2, 2), (3, 3), (4, 4), (5, 5), (3, 5), (2, 5), (5, 6)])
+# every (P, Q) pair the kernels are instantiated for
+@pytest.mark.parametrize("P,Q", [(2, 2), (2, 3), (2, 4), (2, 5), (3, 3), (3, 4), (3, 5), (4, 4), (4, 5),
+                                 (5, 5), (5, 6)])
 def test_tabulation_matches_oracle(L, P, Q):
     from paper_2204_01722_amd.binding import hpmg_basis_tabulate
     t = hpmg_basis_tabulate(P, Q)
@@ -47,7 +49,7 @@ def test_tabulation_matches_oracle(L, P, Q):
     np.testing.assert_allclose(t["colloc"] @ t["interp"], t["grad"], atol=5e-13)
 
 
-@pytest.mark.parametrize("Pf,Pc", [(3, 2), (5, 3), (5, 2), (4, 3), (5, 4)])
+@pytest.mark.parametrize("Pf,Pc", [(3, 2), (4, 2), (5, 2), (4, 3), (5, 3), (5, 4)])  # every instantiated pair
 def test_ctof_matches_oracle(L, Pf, Pc):
     from paper_2204_01722_amd.binding import hpmg_basis_ctof
     M = hpmg_basis_ctof(Pf, Pc)
