@@ -5,7 +5,6 @@ import numpy as np
 import pytest
 
 from _support import LAM, MU, ensure_built, gpu_available, incident_elements, print_case, rel, report, t2n
-from oracle import basis as obasis
 from oracle import fem, mg as omg
 from paper_2204_01722_amd import inputs
 
