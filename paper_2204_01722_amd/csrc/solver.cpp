@@ -374,7 +374,6 @@ int set_state(hpmg_mg_s *mg, const double *u, hipStream_t s) {
 int do_setup(hpmg_mg_s *mg, const double *const *seeds, hipStream_t s) {
   int st;
   const int prec = prec_of(mg);
-  hpmg_op_s *fine = mg->lv[0].op;
   for (Level &L : mg->lv) {
     hpmg_op_s *o = L.op;
     if (o->fine) continue;  // Galerkin coarse level: shares the fine state
